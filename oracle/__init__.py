@@ -1,0 +1,293 @@
+"""CPU oracle of the spectral-quadrature density path (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are the only users.  The product library never
+imports, links or runs anything under ``oracle/``.
+
+The arithmetic lives in plain C (``sq_oracle.c``, FP64, one routine per step of
+the method); this module only marshals numpy arrays into it, plus the two steps
+that are plain library calls (the tridiagonal eigenvalues of the Lanczos matrix
+and nothing else).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sq_oracle.c")
+_LIB = os.path.join(_HERE, "_liboracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (it is CPU code; no GPU toolchain involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC,
+                               "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double * 3), ("r", C.c_int32),
+                ("bc", C.c_int32), ("pad", C.c_int32 * 3), ("n_atoms", C.c_int32),
+                ("n_proj", C.c_int32), ("sup_off", C.c_void_p), ("sup_idx", C.c_void_p),
+                ("chi", C.c_void_p), ("dchi", C.c_void_p), ("c", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        P, D, I64, I32, VP = C.POINTER(_Problem), C.c_double, C.c_int64, C.c_int32, C.c_void_p
+        L.orc_fd_weights.argtypes = [C.c_int, VP]
+        L.orc_moments.argtypes = [P, VP, D, D, VP, VP, VP, I64, C.c_int, VP]
+        L.orc_moments.restype = C.c_int
+        L.orc_apply_node.argtypes = [P, VP, I64, VP, D, D, VP, VP, VP, VP]
+        L.orc_apply_node.restype = C.c_int
+        L.orc_node_box.argtypes = [P, I64, VP, VP, VP, VP]
+        L.orc_node_box.restype = C.c_int
+        L.orc_cheb_coeffs.argtypes = [C.c_int, D, D, D, D, C.c_int, VP]
+        L.orc_cheb_coeffs.restype = I64
+        L.orc_contract.argtypes = [VP, I64, C.c_int, VP, VP, VP, VP]
+        L.orc_electron_count.argtypes = [VP, C.c_int, D, D, D, D]
+        L.orc_electron_count.restype = D
+        L.orc_fermi_level.argtypes = [VP, C.c_int, D, D, D, D, D, C.c_int, VP, VP]
+        L.orc_fermi_level.restype = C.c_int
+        L.orc_adjoint.argtypes = [P, VP, D, D, VP, VP, VP, I64, C.c_int, VP, VP, VP]
+        L.orc_adjoint.restype = C.c_int
+        L.orc_apply_full.argtypes = [P, VP, VP, VP]
+        L.orc_lanczos.argtypes = [P, VP, C.c_int, C.c_uint64, VP, VP]
+        L.orc_lanczos.restype = C.c_int
+        L.orc_gershgorin.argtypes = [P, VP, VP, VP]
+        L.orc_splitmix_uniform.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_splitmix_uniform.restype = D
+        L.orc_num_threads.restype = C.c_int
+        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_splitmix64.restype = C.c_uint64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _Bound:
+    """A problem marshalled for the C side (keeps the arrays alive)."""
+
+    def __init__(self, prob):
+        self.keep = []
+
+        def arr(x, dt):
+            if x is None:
+                return None
+            y = np.ascontiguousarray(x, dtype=dt)
+            self.keep.append(y)
+            return y
+
+        s = _Problem()
+        s.n[:] = [int(x) for x in prob.n]
+        s.h[:] = [float(x) for x in prob.h]
+        s.r = prob.fd_order // 2
+        s.bc = prob.bc
+        s.pad[:] = [int(x) for x in prob.pad]
+        s.n_atoms = int(prob.n_atoms)
+        s.n_proj = int(prob.n_proj)
+        if prob.n_atoms:
+            s.sup_off = _ptr(arr(prob.sup_off, np.int64))
+            s.sup_idx = _ptr(arr(prob.sup_idx, np.int64))
+            s.chi = _ptr(arr(prob.chi, np.float64))
+            s.dchi = _ptr(arr(prob.dchi, np.float64))
+            s.c = _ptr(arr(prob.c, np.float64))
+        self.s = s
+        self.V = arr(prob.V, np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def fd_weights(r: int) -> np.ndarray:
+    w = np.zeros(r + 1)
+    lib().orc_fd_weights(r, w.ctypes.data)
+    return w
+
+
+def _nodes_and_widths(prob, nodes, node_m):
+    nodes = prob.node_list() if nodes is None else np.asarray(nodes, np.int64)
+    if node_m is None:
+        node_m = prob.node_widths() if (prob.nodes is not None and nodes is prob.nodes) else None
+    mdef = np.asarray(prob.rcut, np.int32)
+    nm = None if node_m is None else np.ascontiguousarray(node_m, dtype=np.int32)
+    return np.ascontiguousarray(nodes), nm, mdef
+
+
+def moments(prob, lmin, lmax, nodes=None, node_m=None, V=None, K=None) -> np.ndarray:
+    """mu[q, k] = e_q^T T_k(Hs_q) e_q for the given nodes (default: the problem's)."""
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    K = prob.order if K is None else K
+    nodes, nm, mdef = _nodes_and_widths(prob, nodes, node_m)
+    mu = np.zeros((nodes.size, K + 1))
+    rc = lib().orc_moments(C.byref(b.s), Vv.ctypes.data, float(lmin), float(lmax),
+                           nodes.ctypes.data, _ptr(nm), mdef.ctypes.data, nodes.size, K,
+                           mu.ctypes.data)
+    if rc:
+        raise ValueError("oracle: invalid node region or parameters")
+    return mu
+
+
+def apply_node(prob, node, m, lmin, lmax, v=None, V=None):
+    """(dims, centre index, Hs_q v) for one node; v flattened over the box (x fastest)."""
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    m = np.ascontiguousarray(m, np.int32)
+    dim = np.zeros(3, np.int32)
+    ctr = np.zeros(1, np.int64)
+    out = None
+    if v is not None:
+        v = np.ascontiguousarray(v, np.float64)
+        out = np.zeros_like(v)
+    rc = lib().orc_apply_node(C.byref(b.s), Vv.ctypes.data, int(node), m.ctypes.data,
+                              float(lmin), float(lmax), _ptr(v), _ptr(out), dim.ctypes.data,
+                              ctr.ctypes.data)
+    if rc:
+        raise ValueError("oracle: invalid node region")
+    return tuple(int(x) for x in dim), int(ctr[0]), out
+
+
+def node_dense(prob, node, m, lmin, lmax, V=None):
+    """Dense Hs_q assembled column by column from the matrix-free product."""
+    dims, ctr, _ = apply_node(prob, node, m, lmin, lmax, V=V)
+    npts = dims[0] * dims[1] * dims[2]
+    H = np.zeros((npts, npts))
+    e = np.zeros(npts)
+    for j in range(npts):
+        e[:] = 0.0
+        e[j] = 1.0
+        H[:, j] = apply_node(prob, node, m, lmin, lmax, e, V=V)[2]
+    return H, dims, ctr
+
+
+def node_box(prob, node, m):
+    b = _Bound(prob)
+    m = np.ascontiguousarray(m, np.int32)
+    lo = np.zeros(3, np.int64)
+    dim = np.zeros(3, np.int32)
+    ctr = np.zeros(3, np.int32)
+    if lib().orc_node_box(C.byref(b.s), int(node), m.ctypes.data, lo.ctypes.data,
+                          dim.ctypes.data, ctr.ctypes.data):
+        raise ValueError("oracle: invalid node region")
+    return lo, dim, ctr
+
+
+KIND_G, KIND_U, KIND_DG, KIND_DU = 0, 1, 2, 3
+
+
+def cheb_coeffs(kind, lambda_f, kT, lmin, lmax, K):
+    """c_k (kind 0), d_k (kind 1) and their lambda_f derivatives (kinds 2, 3)."""
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    out = np.zeros(K + 1)
+    N = lib().orc_cheb_coeffs(kind, (lambda_f - omega) / tau, kT / tau, tau, omega, K,
+                              out.ctypes.data)
+    return out, int(N)
+
+
+def contract(mu, c, d):
+    mu = np.ascontiguousarray(mu, np.float64)
+    n, K1 = mu.shape
+    rho, u = np.zeros(n), np.zeros(n)
+    lib().orc_contract(mu.ctypes.data, n, K1 - 1, np.ascontiguousarray(c).ctypes.data,
+                       np.ascontiguousarray(d).ctypes.data, rho.ctypes.data, u.ctypes.data)
+    return rho, u
+
+
+def electron_count(M, lambda_f, kT, lmin, lmax):
+    M = np.ascontiguousarray(M, np.float64)
+    return float(lib().orc_electron_count(M.ctypes.data, M.size - 1, float(lambda_f), float(kT),
+                                          float(lmin), float(lmax)))
+
+
+class NotBracketed(RuntimeError):
+    pass
+
+
+def fermi_level(M, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
+    M = np.ascontiguousarray(M, np.float64)
+    lf = np.zeros(1)
+    it = np.zeros(1, np.int32)
+    rc = lib().orc_fermi_level(M.ctypes.data, M.size - 1, float(kT), float(lmin), float(lmax),
+                               float(Ne), float(tol), int(max_iter), lf.ctypes.data,
+                               it.ctypes.data)
+    if rc == -4:
+        raise NotBracketed("electron count not bracketed by [lambda_min, lambda_max]")
+    return float(lf[0]), int(it[0])
+
+
+def adjoint(prob, lmin, lmax, a, nodes=None, node_m=None, V=None, with_dR=True):
+    """(dV, dR) of y = sum_q sum_k a[q,k] mu_k^q at fixed lambda_f, omega, tau."""
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    nodes, nm, mdef = _nodes_and_widths(prob, nodes, node_m)
+    a = np.ascontiguousarray(a, np.float64)
+    K = a.shape[1] - 1
+    gV = np.zeros(Vv.size)
+    dR = np.zeros((max(prob.n_atoms, 1), 3)) if with_dR else None
+    rc = lib().orc_adjoint(C.byref(b.s), Vv.ctypes.data, float(lmin), float(lmax),
+                           nodes.ctypes.data, _ptr(nm), mdef.ctypes.data, nodes.size, K,
+                           a.ctypes.data, gV.ctypes.data, _ptr(dR))
+    if rc:
+        raise ValueError("oracle: invalid node region or parameters")
+    return gV, (dR[:prob.n_atoms] if with_dR else None)
+
+
+def apply_full(prob, v, V=None):
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    out = np.zeros_like(v)
+    lib().orc_apply_full(C.byref(b.s), Vv.ctypes.data, v.ctypes.data, out.ctypes.data)
+    return out
+
+
+def splitmix64(seed, i):
+    return int(lib().orc_splitmix64(seed, i))
+
+
+def splitmix_uniform(seed, n):
+    L = lib()
+    return np.array([L.orc_splitmix_uniform(seed, i) for i in range(n)])
+
+
+def lanczos_tridiag(prob, steps, seed, V=None):
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    al, be = np.zeros(steps), np.zeros(max(steps - 1, 1))
+    lib().orc_lanczos(C.byref(b.s), Vv.ctypes.data, steps, seed, al.ctypes.data, be.ctypes.data)
+    return al, be[:steps - 1]
+
+
+def lanczos_bounds(prob, steps=120, seed=0x5EED, margin=0.01, V=None):
+    """Extreme Ritz values of the whole-domain H, widened by margin * width each side."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    al, be = lanczos_tridiag(prob, steps, seed, V=V)
+    ev = eigvalsh_tridiagonal(al, be)
+    lo, hi = float(ev[0]), float(ev[-1])
+    wdt = hi - lo
+    return lo - margin * wdt, hi + margin * wdt
+
+
+def gershgorin(prob, V=None):
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    lo, hi = np.zeros(1), np.zeros(1)
+    lib().orc_gershgorin(C.byref(b.s), Vv.ctypes.data, lo.ctypes.data, hi.ctypes.data)
+    return float(lo[0]), float(hi[0])

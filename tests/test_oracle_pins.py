@@ -1,0 +1,517 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types an oracle formula: each compares the oracle with
+an independent route to the same number (a published table, a closed form, a
+library eigensolver or quadrature, an invariance, a finite difference).
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from numpy.polynomial import chebyshev as npcheb
+
+import oracle as O
+from paper_2011_13517_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tk(k, x):
+    return np.cos(k * np.arccos(np.clip(x, -1.0, 1.0)))
+
+
+def _bounds(prob):
+    return O.lanczos_bounds(prob, steps=80)
+
+
+# --------------------------------------------------------------------------- #
+# finite-difference weights (Section 3, Discretization)
+# --------------------------------------------------------------------------- #
+def test_fd_weights_match_published_table():
+    for line in open(os.path.join(GOLD, "fd_weights.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        tok = line.split()
+        r = int(tok[0])
+        ref = np.array([float(Fraction(t)) for t in tok[1:]])
+        np.testing.assert_allclose(O.fd_weights(r), ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6])
+def test_fd_weights_polynomial_exactness(r):
+    w = O.fd_weights(r)
+    p = np.arange(-r, r + 1)
+    wf = np.concatenate([w[:0:-1], w])
+    for j in range(0, 2 * r + 2):
+        val = float(np.sum(wf * p.astype(float) ** j))
+        exact = 2.0 if j == 2 else 0.0
+        assert abs(val - exact) < 1e-9 * max(1.0, float(r) ** j), (r, j, val)
+    # order is exactly 2r: the first non-vanishing error term appears at degree 2r+2
+    assert abs(float(np.sum(wf * p.astype(float) ** (2 * r + 2)))) > 1e-6
+
+
+# --------------------------------------------------------------------------- #
+# moments: mu_0, mu_1, mu_2 closed forms from the explicit matrix row
+# --------------------------------------------------------------------------- #
+def _explicit_row(prob, node, m, lmin, lmax):
+    """Row q of the scaled node Hamiltonian written entry by entry from the
+    definition of H (Section 2.1): kinetic stencil, local V, h^3 c chi chi^T."""
+    lo, dim, ctr = O.node_box(prob, node, m)
+    N = prob.vshape
+    r = prob.r
+    w = [float(Fraction(t)) for t in _table_row(r)]
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    h = prob.h
+    row = {}
+    cq = tuple(int(lo[a] + ctr[a]) for a in range(3))
+
+    def glin(c):
+        c = list(c)
+        if prob.bc == synth.BC_PERIODIC:
+            c = [c[a] % N[a] for a in range(3)]
+        return c[0] + N[0] * (c[1] + N[1] * c[2])
+
+    def inbox(c):
+        return all(0 <= c[a] - lo[a] < dim[a] for a in range(3))
+
+    gq = glin(cq)
+    diag = -0.5 * sum(w[0] / h[a] ** 2 for a in range(3)) + prob.V[gq]
+    row[cq] = diag
+    for a in range(3):
+        for p in range(1, r + 1):
+            for s in (-1, 1):
+                c = list(cq)
+                c[a] += s * p
+                if inbox(c):
+                    row[tuple(c)] = row.get(tuple(c), 0.0) - 0.5 * w[p] / h[a] ** 2
+    h3 = h[0] * h[1] * h[2]
+    for J in range(prob.n_atoms):
+        s0, s1 = prob.sup_off[J], prob.sup_off[J + 1]
+        idx = prob.sup_idx[s0:s1]
+        hit = np.flatnonzero(idx == gq)
+        if hit.size == 0:
+            continue
+        chq = prob.chi[s0 + hit[0]]
+        for t in range(s0, s1):
+            g = int(prob.sup_idx[t])
+            c = [g % N[0], (g // N[0]) % N[1], g // (N[0] * N[1])]
+            # periodic: bring into the box frame
+            if prob.bc == synth.BC_PERIODIC:
+                c = [lo[a] + ((c[a] - lo[a]) % N[a]) for a in range(3)]
+            if not inbox(c):
+                continue
+            e = h3 * float(np.sum(prob.c[J] * prob.chi[t] * chq))
+            row[tuple(c)] = row.get(tuple(c), 0.0) + e
+    row[cq] -= omega
+    return {k: v / tau for k, v in row.items()}, cq
+
+
+def _table_row(r):
+    for line in open(os.path.join(GOLD, "fd_weights.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        tok = line.split()
+        if int(tok[0]) == r:
+            return tok[1:]
+    raise KeyError(r)
+
+
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET, synth.BC_EMBEDDED])
+def test_low_moments_closed_form(bc):
+    prob = synth.small_problem(11, n=(9, 9, 9), bc=bc, rcut=(3, 3, 3), fd_order=4, n_atoms=4,
+                               rc=1.4)
+    lmin, lmax = O.gershgorin(prob)
+    for node in (0, 40, 364, 700):
+        m = (3, 3, 3)
+        mu = O.moments(prob, lmin, lmax, nodes=[node], node_m=[m], K=2)[0]
+        row, cq = _explicit_row(prob, node, m, lmin, lmax)
+        assert mu[0] == 1.0
+        assert abs(mu[1] - row[cq]) < 1e-14
+        mu2 = 2.0 * sum(v * v for v in row.values()) - 1.0        # T_2(x) = 2x^2 - 1
+        assert abs(mu[2] - mu2) < 1e-13, (node, mu[2], mu2)
+
+
+# --------------------------------------------------------------------------- #
+# spectral theorem (Section 2.2): mu_k = sum_i U_qi^2 T_k(lambda_i) via eigh
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET, synth.BC_EMBEDDED])
+def test_recurrence_matches_eigendecomposition(bc):
+    prob = synth.small_problem(5, n=(8, 8, 8), bc=bc, rcut=(2, 2, 2), n_atoms=3, rc=1.3)
+    lmin, lmax = _bounds(prob)
+    K = 30
+    for node in (0, 7, 200, 511):
+        H, dims, ctr = O.node_dense(prob, node, (2, 2, 2), lmin, lmax)
+        assert np.abs(H - H.T).max() < 1e-15
+        lam, U = np.linalg.eigh(H)
+        assert lam.min() > -1 and lam.max() < 1
+        ref = np.array([np.sum(U[ctr] ** 2 * _tk(k, lam)) for k in range(K + 1)])
+        mu = O.moments(prob, lmin, lmax, nodes=[node], node_m=[(2, 2, 2)], K=K)[0]
+        np.testing.assert_allclose(mu, ref, rtol=0, atol=5e-13)
+        assert np.all(np.abs(mu) <= 1.0 + 1e-12)
+
+
+def test_full_trace_identity_dirichlet():
+    """Box covering the whole Dirichlet domain: H^q = H for every q, so
+    sum_q mu_k^q = Tr T_k(Hs) = sum_i T_k(lambda_i)."""
+    prob = synth.small_problem(21, n=(6, 5, 4), bc=synth.BC_DIRICHLET, rcut=(6, 6, 6), n_atoms=2,
+                               rc=1.2, fd_order=6)
+    n = int(np.prod(prob.n))
+    Hfull = np.stack([O.apply_full(prob, np.eye(n)[j]) for j in range(n)], 1)
+    lmin, lmax = O.gershgorin(prob)
+    lam = np.linalg.eigvalsh((Hfull - 0.5 * (lmax + lmin) * np.eye(n)) / (0.5 * (lmax - lmin)))
+    mu = O.moments(prob, lmin, lmax, K=25)
+    tr = np.array([np.sum(_tk(k, lam)) for k in range(26)])
+    np.testing.assert_allclose(mu.sum(0), tr, rtol=0, atol=1e-11)
+
+
+# --------------------------------------------------------------------------- #
+# separable closed form: constant V, no projectors -> Kronecker sum of 1-D stencils
+# --------------------------------------------------------------------------- #
+def test_separable_dst_closed_form_r1():
+    """r = 1: 1-D truncated stencil is tridiag(-1/2, 1, -1/2)/h^2 with the DST-I
+    eigenpairs lambda_j = (1 - cos(pi j/(b+1)))/h^2, u_j(i) ~ sin(pi i j/(b+1))."""
+    n, h = (11, 11, 11), (0.5, 0.6, 0.7)
+    prob = synth.build_problem("sep", n, h, 2, synth.BC_DIRICHLET, (3, 3, 3), 20, 0.1,
+                               np.zeros((0, 3)), np.zeros(0), with_projectors=False)
+    prob.V = np.full(int(np.prod(n)), -0.3)
+    lmin, lmax = -0.5, 20.0
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    node = 5 + 11 * (5 + 11 * 5)
+    b = 7
+    j = np.arange(1, b + 1)
+    ev, vec = [], []
+    for a in range(3):
+        ev.append((1 - np.cos(np.pi * j / (b + 1))) / h[a] ** 2)
+        u = np.sin(np.pi * np.outer(np.arange(1, b + 1), j) / (b + 1))
+        vec.append(u / np.linalg.norm(u, axis=0))
+    c = 3   # centre index in each 1-D factor
+    lam = (ev[0][:, None, None] + ev[1][None, :, None] + ev[2][None, None, :] - 0.3 - omega) / tau
+    wgt = (vec[0][c] ** 2)[:, None, None] * (vec[1][c] ** 2)[None, :, None] * (vec[2][c] ** 2)[None, None, :]
+    ref = np.array([np.sum(wgt * _tk(k, lam)) for k in range(21)])
+    mu = O.moments(prob, lmin, lmax, nodes=[node], node_m=[(3, 3, 3)], K=20)[0]
+    np.testing.assert_allclose(mu, ref, rtol=0, atol=1e-13)
+
+
+def test_separable_high_order_via_1d_eigh():
+    n, h = (14, 14, 14), (0.45, 0.45, 0.45)
+    prob = synth.build_problem("sep6", n, h, 12, synth.BC_PERIODIC, (3, 3, 3), 25, 0.1,
+                               np.zeros((0, 3)), np.zeros(0), with_projectors=False)
+    prob.V = np.full(int(np.prod(n)), 0.2)
+    w = [float(Fraction(t)) for t in _table_row(6)]
+    b = 7
+    T = np.zeros((b, b))
+    for i in range(b):
+        T[i, i] = -0.5 * w[0] / h[0] ** 2
+        for p in range(1, 7):
+            for s in (-1, 1):
+                if 0 <= i + s * p < b:
+                    T[i, i + s * p] = -0.5 * w[p] / h[0] ** 2
+    ev, U = np.linalg.eigh(T)
+    lmin, lmax = -1.0, 3 * 30.0
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    lam = (ev[:, None, None] + ev[None, :, None] + ev[None, None, :] + 0.2 - omega) / tau
+    u2 = U[3] ** 2
+    wgt = u2[:, None, None] * u2[None, :, None] * u2[None, None, :]
+    ref = np.array([np.sum(wgt * _tk(k, lam)) for k in range(26)])
+    mu = O.moments(prob, lmin, lmax, nodes=[100], node_m=[(3, 3, 3)], K=25)[0]
+    np.testing.assert_allclose(mu, ref, rtol=0, atol=2e-13)
+
+
+# --------------------------------------------------------------------------- #
+# invariances
+# --------------------------------------------------------------------------- #
+def test_constant_shift_invariance():
+    prob = synth.small_problem(8, n=(10, 10, 10), rcut=(3, 3, 3), n_atoms=3)
+    lmin, lmax = _bounds(prob)
+    nodes = [0, 123, 555, 999]
+    mu = O.moments(prob, lmin, lmax, nodes=nodes, K=20)
+    s = 0.37
+    mu2 = O.moments(prob, lmin + s, lmax + s, nodes=nodes, K=20, V=prob.V + s)
+    np.testing.assert_allclose(mu2, mu, rtol=0, atol=1e-14)
+    lf = 0.5 * (lmin + lmax) - 0.2 * (lmax - lmin)
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, 0.2, lmin, lmax, 20)
+    d, _ = O.cheb_coeffs(O.KIND_U, lf, 0.2, lmin, lmax, 20)
+    c2, _ = O.cheb_coeffs(O.KIND_G, lf + s, 0.2, lmin + s, lmax + s, 20)
+    d2, _ = O.cheb_coeffs(O.KIND_U, lf + s, 0.2, lmin + s, lmax + s, 20)
+    rho, u = O.contract(mu, c, d)
+    rho2, u2 = O.contract(mu2, c2, d2)
+    np.testing.assert_allclose(rho2, rho, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(u2, u + s * rho, rtol=0, atol=1e-12)
+
+
+def _shifted_problem(prob, shift):
+    """Periodic translation of the potential and of every atom by whole nodes."""
+    n = prob.n
+    V = prob.V.reshape(n[2], n[1], n[0])
+    V2 = np.roll(V, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2)).reshape(-1)
+    q = prob.sup_idx
+    i, j, k = q % n[0], (q // n[0]) % n[1], q // (n[0] * n[1])
+    q2 = (i + shift[0]) % n[0] + n[0] * (((j + shift[1]) % n[1]) + n[1] * ((k + shift[2]) % n[2]))
+    import dataclasses
+    return dataclasses.replace(prob, V=V2, sup_idx=q2.astype(np.int64))
+
+
+def test_periodic_translation_equivariance():
+    prob = synth.small_problem(9, n=(9, 10, 11), rcut=(3, 3, 3), n_atoms=3)
+    lmin, lmax = _bounds(prob)
+    shift = (2, 3, 5)
+    prob2 = _shifted_problem(prob, shift)
+    nodes = np.array([0, 17, 301, 640, 989])
+    n = prob.n
+    i, j, k = nodes % n[0], (nodes // n[0]) % n[1], nodes // (n[0] * n[1])
+    nodes2 = (i + shift[0]) % n[0] + n[0] * (((j + shift[1]) % n[1]) + n[1] * ((k + shift[2]) % n[2]))
+    mu = O.moments(prob, lmin, lmax, nodes=nodes, K=16)
+    mu2 = O.moments(prob2, lmin, lmax, nodes=nodes2, K=16)
+    np.testing.assert_allclose(mu2, mu, rtol=0, atol=1e-13)
+
+
+def test_axis_permutation_equivariance():
+    prob = synth.small_problem(12, n=(9, 9, 9), rcut=(3, 3, 3), with_projectors=False)
+    lmin, lmax = _bounds(prob)
+    V = prob.V.reshape(9, 9, 9)          # [k][j][i]
+    import dataclasses
+    prob2 = dataclasses.replace(prob, V=np.ascontiguousarray(V.transpose(2, 1, 0)).reshape(-1))
+    nodes = np.array([3, 50, 402, 700])
+    i, j, k = nodes % 9, (nodes // 9) % 9, nodes // 81
+    nodes2 = k + 9 * (j + 9 * i)
+    mu = O.moments(prob, lmin, lmax, nodes=nodes, K=16)
+    mu2 = O.moments(prob2, lmin, lmax, nodes=nodes2, K=16)
+    np.testing.assert_allclose(mu2, mu, rtol=0, atol=1e-13)
+
+
+def test_disjoint_node_sets_add():
+    prob = synth.small_problem(13, n=(8, 8, 8), rcut=(2, 2, 2))
+    lmin, lmax = _bounds(prob)
+    a = O.moments(prob, lmin, lmax, nodes=np.arange(0, 200), K=10).sum(0)
+    b = O.moments(prob, lmin, lmax, nodes=np.arange(200, 512), K=10).sum(0)
+    t = O.moments(prob, lmin, lmax, K=10).sum(0)
+    np.testing.assert_allclose(a + b, t, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------- #
+# Chebyshev coefficients, Eq. (ChebyshevWeights)
+# --------------------------------------------------------------------------- #
+def test_coefficients_vs_adaptive_quadrature():
+    from scipy.integrate import quad
+    lmin, lmax, lf, kT, K = -1.0, 3.0, 0.4, 0.05, 12
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, kT, lmin, lmax, K)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    lfh, th = (lf - omega) / tau, kT / tau
+    g = lambda x: 1.0 / (1.0 + np.exp((x - lfh) / th))
+    t0 = np.arccos(lfh)
+    for k in range(K + 1):
+        f = lambda t: g(np.cos(t)) * np.cos(k * t)
+        val = (quad(f, 0, t0, epsabs=1e-15, epsrel=1e-14, limit=400)[0]
+               + quad(f, t0, np.pi, epsabs=1e-15, epsrel=1e-14, limit=400)[0]) * 2 / np.pi
+        assert abs(val - c[k]) < 1e-13, (k, val, c[k])
+
+
+def test_coefficients_step_limit_closed_form():
+    """theta -> 0: g -> step, c_0 = 2 - 2 acos(lf)/pi, c_k = -(2/(pi k)) sin(k acos(lf));
+    the Fermi smoothing changes c_k only at second order in theta."""
+    lmin, lmax, K = -1.0, 1.0, 20
+    lf = 0.3
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, 1e-5, lmin, lmax, K)
+    t = np.arccos(lf)
+    k = np.arange(1, K + 1)
+    np.testing.assert_allclose(c[0], 2 - 2 * t / np.pi, atol=1e-8)
+    np.testing.assert_allclose(c[1:], -(2 / (np.pi * k)) * np.sin(k * t), atol=1e-8)
+
+
+def test_coefficient_limits_full_and_empty():
+    c, _ = O.cheb_coeffs(O.KIND_G, 50.0, 0.01, -1.0, 1.0, 15)
+    assert abs(c[0] - 2.0) < 1e-14 and np.abs(c[1:]).max() < 1e-14
+    c, _ = O.cheb_coeffs(O.KIND_G, -50.0, 0.01, -1.0, 1.0, 15)
+    assert np.abs(c).max() < 1e-14
+
+
+def test_band_energy_coefficients_three_term_identity():
+    """x T_k = (T_{k+1} + T_{|k-1|})/2, so the coefficients of (tau x + omega) g are
+    d_k = tau (c_{k-1} + c_{k+1})/2 + omega c_k for k >= 1, d_0 = tau c_1 + omega c_0."""
+    lmin, lmax, lf, kT, K = -2.0, 6.0, 0.5, 0.08, 30
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, kT, lmin, lmax, K + 1)
+    d, _ = O.cheb_coeffs(O.KIND_U, lf, kT, lmin, lmax, K)
+    ref = np.empty(K + 1)
+    ref[0] = tau * c[1] + omega * c[0]
+    ref[1:] = tau * 0.5 * (c[0:K] + c[2:K + 2]) + omega * c[1:K + 1]
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-13)
+
+
+def test_coefficient_lambda_derivatives_vs_central_difference():
+    lmin, lmax, lf, kT, K = -2.0, 6.0, 0.5, 0.08, 20
+    dl = 1e-5
+    for kind, dkind in ((O.KIND_G, O.KIND_DG), (O.KIND_U, O.KIND_DU)):
+        cp, _ = O.cheb_coeffs(kind, lf + dl, kT, lmin, lmax, K)
+        cm, _ = O.cheb_coeffs(kind, lf - dl, kT, lmin, lmax, K)
+        dc, _ = O.cheb_coeffs(dkind, lf, kT, lmin, lmax, K)
+        np.testing.assert_allclose(dc, (cp - cm) / (2 * dl), rtol=0, atol=2e-8)
+
+
+def test_expansion_converges_to_fermi_function_on_eigenvalues():
+    """As K grows, rho^q -> 2 sum_i U_qi^2 g(lambda_i) at the Bernstein-ellipse rate."""
+    prob = synth.small_problem(14, n=(7, 7, 7), rcut=(2, 2, 2), n_atoms=2, rc=1.2)
+    lmin, lmax = _bounds(prob)
+    kT, lf = 1.0, 0.5 * (lmin + lmax) - 0.25 * (lmax - lmin)
+    H, dims, ctr = O.node_dense(prob, 100, (2, 2, 2), lmin, lmax)
+    lam, U = np.linalg.eigh(H)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    g = 1.0 / (1.0 + np.exp((lam * tau + omega - lf) / kT))
+    exact = 2.0 * np.sum(U[ctr] ** 2 * g)
+    errs = []
+    for K in (20, 40, 80, 160):
+        mu = O.moments(prob, lmin, lmax, nodes=[100], node_m=[(2, 2, 2)], K=K)
+        c, _ = O.cheb_coeffs(O.KIND_G, lf, kT, lmin, lmax, K)
+        rho, _ = O.contract(mu, c, c)
+        errs.append(abs(rho[0] - exact))
+    assert errs[-1] < 1e-12
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+    # rate bound: error <~ exp(-K * pi * th / sqrt(1 - lf^2)) up to a constant
+    lfh, th = (lf - omega) / tau, kT / tau
+    rate = np.pi * th / np.sqrt(1 - lfh ** 2)
+    assert errs[2] < 50 * np.exp(-80 * rate)
+
+
+# --------------------------------------------------------------------------- #
+# Fermi level, Eq. (Ne)
+# --------------------------------------------------------------------------- #
+def test_fermi_level_hits_electron_count_and_brute_force_scan():
+    prob = synth.small_problem(15, n=(8, 8, 8), rcut=(2, 2, 2), order=30, kT=0.2)
+    lmin, lmax = _bounds(prob)
+    mu = O.moments(prob, lmin, lmax)
+    M = mu.sum(0)
+    Ne = 40.0
+    lf, it = O.fermi_level(M, prob.kT, lmin, lmax, Ne, tol=1e-10)
+    assert it > 0
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, prob.kT, lmin, lmax, prob.order)
+    rho, _ = O.contract(mu, c, c)
+    assert abs(rho.sum() - Ne) < 1e-9
+    # brute-force scan for the sign change
+    grid = np.linspace(lmin, lmax, 400)
+    ne = np.array([O.electron_count(M, x, prob.kT, lmin, lmax) for x in grid])
+    i = np.flatnonzero((ne[:-1] - Ne) * (ne[1:] - Ne) <= 0)
+    assert i.size >= 1
+    assert any(grid[t] - 1e-12 <= lf <= grid[t + 1] + 1e-12 for t in i)
+    # dN_e/dlambda_f > 0 at the root
+    dc, _ = O.cheb_coeffs(O.KIND_DG, lf, prob.kT, lmin, lmax, prob.order)
+    assert 2 * (0.5 * dc[0] * M[0] + dc[1:] @ M[1:]) > 0
+
+
+def test_fermi_level_not_bracketed():
+    prob = synth.small_problem(16, n=(6, 6, 6), rcut=(1, 1, 1), order=10, kT=0.2,
+                               with_projectors=False)
+    lmin, lmax = _bounds(prob)
+    M = O.moments(prob, lmin, lmax).sum(0)
+    with pytest.raises(O.NotBracketed):
+        O.fermi_level(M, prob.kT, lmin, lmax, 2.0 * 216 + 1.0)
+
+
+def test_config1_electron_count():
+    prob = synth.config(1)
+    lmin, lmax = O.lanczos_bounds(prob, steps=120)
+    mu = O.moments(prob, lmin, lmax)
+    assert np.all(mu[:, 0] == 1.0) and np.abs(mu).max() <= 1.0 + 1e-12
+    lf, _ = O.fermi_level(mu.sum(0), prob.kT, lmin, lmax, prob.Ne, tol=1e-11)
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, prob.kT, lmin, lmax, prob.order)
+    rho, _ = O.contract(mu, c, c)
+    assert abs(rho.sum() - prob.Ne) < 1e-10
+
+
+# --------------------------------------------------------------------------- #
+# spectral bounds
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET, synth.BC_EMBEDDED])
+def test_lanczos_bounds_enclose_spectrum(bc):
+    prob = synth.small_problem(17, n=(7, 7, 6), bc=bc, rcut=(2, 2, 2), n_atoms=3, rc=1.3)
+    N = int(np.prod(prob.vshape))
+    H = np.stack([O.apply_full(prob, np.eye(N)[j]) for j in range(N)], 1)
+    assert np.abs(H - H.T).max() < 1e-12
+    lam = np.linalg.eigvalsh(H)
+    lo, hi = O.lanczos_bounds(prob, steps=120)
+    glo, ghi = O.gershgorin(prob)
+    assert glo <= lam[0] and lam[-1] <= ghi
+    assert lo < lam[0] and lam[-1] < hi
+    assert glo - 0.02 * (ghi - glo) < lo and hi < ghi + 0.02 * (ghi - glo)
+
+
+def test_splitmix64_published_outputs():
+    ref = [int(l, 16) for l in open(os.path.join(GOLD, "splitmix64.txt")) if not l.startswith("#")]
+    assert [O.splitmix64(0, i) for i in range(3)] == ref
+
+
+# --------------------------------------------------------------------------- #
+# adjoint
+# --------------------------------------------------------------------------- #
+def _divided_differences(f, df, lam):
+    L1, L2 = np.meshgrid(lam, lam, indexing="ij")
+    dd = (f(L1) - f(L2)) / np.where(L1 == L2, 1.0, L1 - L2)
+    close = np.abs(L1 - L2) < 1e-9
+    dd[close] = df(0.5 * (L1 + L2))[close]
+    return dd
+
+
+def test_adjoint_matches_daleckii_krein():
+    prob = synth.small_problem(18, n=(8, 8, 8), rcut=(2, 2, 2), n_atoms=3, rc=1.3)
+    lmin, lmax = _bounds(prob)
+    tau = 0.5 * (lmax - lmin)
+    K = 14
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=K + 1)
+    node, m = 77, (2, 2, 2)
+    H, dims, ctr = O.node_dense(prob, node, m, lmin, lmax)
+    lam, U = np.linalg.eigh(H)
+    coef = a.copy()
+    p = lambda x: npcheb.chebval(x, coef)
+    dp = lambda x: npcheb.chebval(x, npcheb.chebder(coef))
+    P = _divided_differences(p, dp, lam)
+    # d/dHs_jj of e_q^T p(Hs) e_q = sum_ab U_ja U_qa P_ab U_qb U_jb
+    G = np.einsum("ja,a,ab,b,jb->j", U, U[ctr], P, U[ctr], U)
+    gV, _ = O.adjoint(prob, lmin, lmax, a[None, :], nodes=[node], node_m=[m], with_dR=False)
+    lo, dim, _ = O.node_box(prob, node, m)
+    N = prob.vshape
+    ii, jj, kk = np.meshgrid(*[np.arange(dim[x]) + lo[x] for x in range(3)], indexing="ij")
+    gl = ((ii % N[0]) + N[0] * ((jj % N[1]) + N[1] * (kk % N[2]))).transpose(2, 1, 0).reshape(-1)
+    np.testing.assert_allclose(gV[gl] * tau, G, rtol=0, atol=1e-12)
+    mask = np.ones(gV.size, bool)
+    mask[gl] = False
+    assert np.all(gV[mask] == 0.0)
+
+
+def test_adjoint_dV_central_difference():
+    prob = synth.small_problem(19, n=(8, 8, 8), rcut=(2, 2, 2), n_atoms=3, rc=1.3, order=16)
+    lmin, lmax = _bounds(prob)
+    rng = np.random.default_rng(1)
+    nodes = np.arange(0, 512, 7)
+    a = rng.normal(size=(nodes.size, prob.order + 1))
+    gV, _ = O.adjoint(prob, lmin, lmax, a, nodes=nodes, with_dR=False)
+    d = np.zeros(prob.V.size)
+    d[rng.choice(prob.V.size, 40, replace=False)] = rng.uniform(-1, 1, 40)
+    eps = 1e-4
+    yp = np.sum(a * O.moments(prob, lmin, lmax, nodes=nodes, V=prob.V + eps * d))
+    ym = np.sum(a * O.moments(prob, lmin, lmax, nodes=nodes, V=prob.V - eps * d))
+    fd = (yp - ym) / (2 * eps)
+    assert abs(fd - gV @ d) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_adjoint_dR_central_difference():
+    import dataclasses
+    prob = synth.small_problem(20, n=(9, 9, 9), rcut=(3, 3, 3), n_atoms=3, rc=1.5, order=12)
+    lmin, lmax = _bounds(prob)
+    rng = np.random.default_rng(2)
+    nodes = np.arange(0, 729, 5)
+    a = rng.normal(size=(nodes.size, prob.order + 1))
+    _, dR = O.adjoint(prob, lmin, lmax, a, nodes=nodes)
+    eps = 1e-4
+    for J in range(prob.n_atoms):
+        for x in range(3):
+            ys = []
+            for s in (1, -1):
+                pos = prob.atom_pos.copy()
+                pos[J, x] += s * eps
+                off, idx, chi, dchi = synth.projector_tables(prob.n, prob.h, prob.pad, pos,
+                                                             prob.bc, rc=1.5)
+                p2 = dataclasses.replace(prob, sup_off=off, sup_idx=idx, chi=chi, dchi=dchi)
+                ys.append(np.sum(a * O.moments(p2, lmin, lmax, nodes=nodes)))
+            fd = (ys[0] - ys[1]) / (2 * eps)
+            assert abs(fd - dR[J, x]) < 1e-6 * max(1.0, abs(fd)), (J, x, fd, dR[J, x])
