@@ -1,0 +1,216 @@
+"""Benchmark of the spectral-quadrature hot path on one MI355X.
+
+One step = the whole path over the 64^3 Mg-like workload (96 atoms x 4
+projectors, 27^3 node regions, K = 100, kT = 0.001 Ha, N_e = 192):
+  spectral bounds (device FP64 Lanczos) -> scaled diagonal -> FP32 region
+  recurrence with FP64 moments -> moment sum -> FP64 Fermi bisection ->
+  coefficients -> pointwise rho, u -> adjoint (dV, dR).
+Inputs are resident in HBM before the timed region.  Throughput is counted in
+node-steps (one node advanced by one Chebyshev order; K per node per step).
+
+Prints one JSON line (rank 0).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9   # non-packed FP32 FMA: 78.6 TFLOP/s
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2011_13517_amd import sq, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    prob = synth.config(args.config)
+    log(f"workload {prob.name}: {prob.n_nodes} nodes, K={prob.order}, atoms={prob.n_atoms}")
+    ctx = sq.Context(prob, precision=1, adjoint_precision=1)
+    info = ctx.info
+    K = ctx.K
+    n_nodes = ctx.n_nodes
+    region_points = int(info.region_points)
+    V = torch.tensor(prob.V, dtype=torch.float64, device=dev)
+    g_rho = torch.ones(n_nodes, dtype=torch.float64, device=dev)
+    g_u = torch.ones(n_nodes, dtype=torch.float64, device=dev)
+    dV = torch.zeros_like(V)
+    dR = torch.zeros((max(prob.n_atoms, 1), 3), dtype=torch.float64, device=dev)
+    mu = torch.empty((n_nodes, K + 1), dtype=torch.float64, device=dev)
+    M = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    lam = torch.zeros(1, dtype=torch.float64, device=dev)
+    Ne = prob.Ne if prob.Ne is not None else 0.0
+    max_iter = 200 if prob.Ne is not None else 0
+    if max_iter == 0:
+        lam.fill_(prob.lambda_f)
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("fwd", "bwd")}
+    times = {"fwd": [], "bwd": []}
+
+    def step(timed):
+        if timed:
+            ev["fwd"][0].record()
+        ctx.density(V, math.nan, math.nan, moments=mu, moment_sum=M)
+        if timed:
+            ev["fwd"][1].record()
+        out = ctx.fermi_level(Ne=Ne, tol=1e-8, max_iter=max_iter, lambda_f=lam, device=dev)
+        if timed:
+            ev["bwd"][0].record()
+        ctx.backward(g_rho, g_u, dV, dR if prob.n_atoms else None)
+        if timed:
+            ev["bwd"][1].record()
+        return out
+
+    for w in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out = step(True)
+        torch.cuda.synchronize()
+        times["fwd"].append(ev["fwd"][0].elapsed_time(ev["fwd"][1]) * 1e-3)
+        times["bwd"].append(ev["bwd"][0].elapsed_time(ev["bwd"][1]) * 1e-3)
+        log(f"step {s + 1}/{args.steps}: forward {times['fwd'][-1]:.3f} s, "
+            f"adjoint {times['bwd'][-1]:.3f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = n_nodes * K * args.steps / wall
+    lam_v, rho, u, tot = out
+    tot = tot.cpu().numpy()
+    ctx.status()
+    log(f"timed {args.steps} steps in {wall:.3f} s -> {value:.4e} node-steps/s; "
+        f"N_e={tot[0]:.10f} lambda_f={lam_v.item():.10f} iters={int(tot[6])}")
+
+    # roofline of the two region kernels (VALU-bound: the region state stays on chip)
+    r = prob.fd_order // 2
+    flops_fwd = region_points * K * (9 * r + 2)           # stencil: 3r adds + 3r FMAs + 1 FMA
+    flops_bwd = region_points * K * (3 * (9 * r + 2) + 2)  # forward again, rebuild, adjoint, dV
+    t_fwd = float(np.mean(times["fwd"]))
+    t_bwd = float(np.mean(times["bwd"]))
+    rf = dict(bound="alu", achieved=flops_fwd / t_fwd / 1e12, peak=PEAK_FP32_VALU / 1e12,
+              unit="TFLOP/s", traffic=None)
+    rb = dict(bound="alu", achieved=flops_bwd / t_bwd / 1e12, peak=PEAK_FP32_VALU / 1e12,
+              unit="TFLOP/s", traffic=None)
+    for d in (rf, rb):
+        d["frac"] = d["achieved"] / d["peak"]
+    dominant, other = (rb, rf) if t_bwd >= t_fwd else (rf, rb)
+    dominant = dict(dominant, kernel="cheb_adjoint_kernel" if dominant is rb else
+                    "cheb_forward_kernel")
+    other = dict(other, kernel="cheb_forward_kernel" if dominant is rb else "cheb_adjoint_kernel")
+
+    # accuracy against the FP64 oracle on sampled nodes
+    extra = {}
+    rho_np = rho.cpu().numpy()
+    tot_om, tot_tau = float(tot[4]), float(tot[5])
+    lmin, lmax = tot_om - tot_tau, tot_om + tot_tau
+    import oracle as O
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(n_nodes, args.cpu_sample, replace=False))
+    t_o = time.perf_counter()
+    mu_ref = O.moments(prob, lmin, lmax, nodes=prob.node_list()[sample])
+    t_oracle_fwd = time.perf_counter() - t_o
+    c, _ = O.cheb_coeffs(O.KIND_G, lam_v.item(), prob.kT, lmin, lmax, K)
+    rho_ref, _ = O.contract(mu_ref, c, c)
+    drho = np.abs(rho_np[sample] - rho_ref)
+    extra["accuracy"] = dict(max_abs_drho=float(drho.max()),
+                             rel_drho=float(drho.max() / np.abs(rho_np).max()),
+                             max_abs_dmu=float(np.abs(mu.cpu().numpy()[sample] - mu_ref).max()),
+                             sample_nodes=int(sample.size), reference="FP64 oracle")
+    log(f"accuracy vs oracle on {sample.size} nodes: max|drho| {drho.max():.3e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        a = np.ones((sample.size, K + 1))
+        t_o = time.perf_counter()
+        O.adjoint(prob, lmin, lmax, a, nodes=prob.node_list()[sample])
+        t_oracle_bwd = time.perf_counter() - t_o
+        t_cpu = t_oracle_fwd + t_oracle_bwd
+        cpu = dict(value=sample.size * K / t_cpu, unit="node-steps/s", cores=O.num_threads(),
+                   kind="oracle",
+                   sample=f"{sample.size} random nodes of the same workload: oracle moments "
+                          f"({t_oracle_fwd:.1f} s) + oracle adjoint ({t_oracle_bwd:.1f} s)")
+        log(f"cpu baseline {cpu['value']:.3e} node-steps/s on {cpu['cores']} threads")
+
+    if not args.no_fp64:
+        ctx64 = sq.Context(prob, precision=0)
+        mu64 = torch.empty_like(mu)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx64.density(V, lmin, lmax, moments=mu64)
+        torch.cuda.synchronize()
+        e0.record()
+        ctx64.density(V, lmin, lmax, moments=mu64)
+        e1.record()
+        torch.cuda.synchronize()
+        t64 = e0.elapsed_time(e1) * 1e-3
+        ctx64.close()
+        extra["fp64_forward"] = dict(seconds=t64, node_steps_per_s=n_nodes * K / t64,
+                                     fp32_speedup=t64 / t_fwd)
+        log(f"FP64 forward {t64:.3f} s vs FP32 forward {t_fwd:.3f} s")
+
+    line = {
+        "metric": "SQ grid-node·Chebyshev-steps/s at 1 GPU; max |Δρ| vs FP64 oracle",
+        "value": value,
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": prob.name,
+            "grid": list(prob.n), "h": list(prob.h), "fd_order": prob.fd_order,
+            "nodes": n_nodes, "region": list(info.max_region), "order": K, "kT": prob.kT,
+            "atoms": prob.n_atoms, "Ne": prob.Ne, "region_points": region_points,
+            "precision": "FP32 recurrence, FP64 moments/coefficients/bisection",
+            "adjoint_precision": "FP32 vectors, FP64 dV/dR accumulation",
+            "step": "Lanczos bounds + forward + Fermi bisection + rho,u + adjoint (dV, dR)",
+        },
+        "roofline": dominant,
+        "roofline_other": other,
+        "times_s": {"forward_mean": t_fwd, "adjoint_mean": t_bwd},
+        "region_point_steps_per_s": region_points * K * args.steps / wall,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * sq.h -- C ABI of the MI355X (gfx950) spectral-quadrature density library.
+ *
+ * Method: linear-scaling spectral quadrature (Ghosh & Bhattacharya, "Spectral
+ * quadrature for the first principles study of crystal defects: application
+ * to magnesium").  For every finite-difference node q the Kohn-Sham
+ * Hamiltonian restricted to the node's region of influence (Section 3,
+ * "Hamiltonian at each grid point"), scaled to [-1, 1] (Section 2.2), drives
+ * the Chebyshev recurrence of Eq. (Chebyshev); the diagonal entries
+ * mu_k^q = e_q^T T_k(Hs_q) e_q ("moments") are contracted with the
+ * Clenshaw-Curtis coefficients of Eq. (ChebyshevWeights) into the pointwise
+ * electron density and band energy of Eqs. (rhoq), (uq); the Fermi level is
+ * fixed by the electron count of Eq. (Ne).
+ *
+ * Conventions for every entry point
+ *  - Every function returns an sq_status (0 = success, < 0 = error) and never
+ *    throws; sq_last_error() returns a thread-local message for the last error.
+ *  - Array arguments named "device" are HIP device pointers owned by the
+ *    caller; arguments named "host" are host pointers read during the call.
+ *  - Grids are flattened with x fastest: idx = i + n0*(j + n1*k).
+ *  - sq_density, sq_fermi_level and sq_density_backward only enqueue work on
+ *    the given stream (a hipStream_t; NULL = the default stream): they never
+ *    synchronise the host and never allocate, so a sequence of them can be
+ *    captured into a HIP graph and replayed.  Argument errors detectable on the
+ *    host are reported at the call; conditions found on the device (Fermi level
+ *    not bracketed, region atom list overflow) are written to the `totals`
+ *    status word and to sq_device_status().
+ *  - A context is not thread-safe; use one context per stream.
+ */
+#ifndef SQ_H
+#define SQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SQ_OK = 0,
+    SQ_ERR_ARG = -1,            /* invalid argument or unsupported shape */
+    SQ_ERR_HIP = -2,            /* a HIP runtime call failed */
+    SQ_ERR_OOM = -3,            /* device allocation failed (sq_setup only) */
+    SQ_ERR_NOT_CONVERGED = -4,  /* Fermi level not bracketed / not converged */
+    SQ_ERR_SPECTRUM = -5,       /* spectral bounds invalid (lambda_max <= lambda_min) */
+    SQ_ERR_STATE = -6           /* call out of order (e.g. backward before forward) */
+} sq_status;
+
+typedef enum {
+    SQ_BC_PERIODIC = 0,   /* wrap; needs 2*rcut_a + 1 + r <= n_a (no self-overlap)        */
+    SQ_BC_DIRICHLET = 1,  /* region clipped at the domain boundary, zero outside          */
+    SQ_BC_EMBEDDED = 2    /* V given on Omega' = Omega padded by rcut_a nodes per side;   */
+                          /* regions never clipped (Section 3, embedded domain Omega')    */
+} sq_bc;
+
+typedef enum {
+    SQ_FP64 = 0,          /* recurrence in FP64 */
+    SQ_FP32_ACC64 = 1     /* recurrence and stencil in FP32, moments and all else FP64 */
+} sq_precision;
+
+/* Problem parameters, following the paper's statement of the problem:
+ * grid n_a and spacing h_a (Section 3, Discretization), FD order n_o (the
+ * Laplacian's central-difference order, radius r = n_o/2), truncation of the
+ * node Hamiltonian to a box of 2*rcut_a + 1 nodes per axis (Section 3, region
+ * of influence), quadrature order K (Section 2.2) and smearing k_B*theta
+ * (Eq. (FermiDirac)). */
+typedef struct {
+    int32_t n[3];        /* Omega grid, nodes per axis (>= 1)                      */
+    double h[3];         /* spacing in bohr (> 0)                                   */
+    int32_t fd_order;    /* even, 2..12 (radius r = fd_order/2)                     */
+    int32_t bc;          /* sq_bc                                                   */
+    int32_t rcut[3];     /* default region half-width in nodes per axis (>= 0)      */
+    int32_t order;       /* Chebyshev degree K, 1..512                              */
+    double kT;           /* smearing in Ha (> 0)                                    */
+    int32_t precision;   /* sq_precision                                            */
+    int32_t ckpt_every;  /* adjoint checkpoint stride in steps (0 -> 10)            */
+    int32_t adjoint_precision;  /* sq_precision of sq_density_backward (default 0 =  */
+                         /* SQ_FP64: the gradient sums cancel strongly, so FP32      */
+                         /* vectors lose ~1e-4 relative at K ~ 80; FP64 adjoint      */
+                         /* supports region edges <= 21, FP32 adjoint edges <= 27)   */
+} sq_params;
+
+/* Nonlocal Kleinman-Bylander projectors (Section 2.1, the nonlocal operator
+ * V_nl(x, x') = sum_J sum_lm c_Jl chi_Jlm(x) chi_Jlm(x'); its action is the
+ * grid sum (V_nl f)(x) = h1 h2 h3 sum_J sum_lm c_Jl chi_Jlm(x) sum_x' chi_Jlm(x') f(x')).
+ * Host arrays, copied by sq_setup.  Supports are lists of grid points. */
+typedef struct {
+    int32_t n_atoms;        /* >= 0                                                  */
+    int32_t n_proj;         /* projectors per atom, 1..4 (e.g. s, px, py, pz)         */
+    const int64_t *sup_off; /* [n_atoms+1] CSR offsets                                */
+    const int64_t *sup_idx; /* [nnz] linear index in V's grid (Omega, or Omega')      */
+    const double *chi;      /* [nnz][n_proj]    chi_Jlm at the support point          */
+    const double *dchi;     /* [nnz][n_proj][3] d chi_Jlm / d R_J, or NULL (no dR)    */
+    const double *c;        /* [n_atoms][n_proj] c_Jl (repeated over m)               */
+} sq_projectors;
+
+typedef struct sq_ctx sq_ctx;
+
+/* Geometry and sizes of a context (filled by sq_get_info). */
+typedef struct {
+    int64_t n_nodes;
+    int32_t order;          /* K: moments per node are K+1                             */
+    int32_t vgrid[3];       /* grid V lives on (Omega, or Omega' for SQ_BC_EMBEDDED)   */
+    int32_t n_atoms;
+    int32_t max_region[3];  /* largest region box                                      */
+    int64_t region_points;  /* sum over nodes of the region size |R_q|                 */
+    int64_t workspace_bytes;/* device memory held by the context                       */
+} sq_info;
+
+/* Builds a context: validates parameters, builds the region work list and
+ * uploads projector tables.  The only call that allocates device memory and
+ * synchronises.
+ *   params      host, required.
+ *   proj        host, NULL for a local-only Hamiltonian.
+ *   nodes       host [n_nodes] linear node indices in Omega, or NULL = every
+ *               node of Omega in linear order (then n_nodes must be n0*n1*n2).
+ *   node_rcut   host [n_nodes][3] per-node half-widths, or NULL = params->rcut.
+ *   out         receives the context (NULL on failure).
+ * Errors: SQ_ERR_ARG (bad shapes, region larger than supported, periodic box
+ * overlapping itself), SQ_ERR_OOM, SQ_ERR_HIP. */
+sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int64_t *nodes,
+                   const int32_t *node_rcut, int64_t n_nodes, sq_ctx **out);
+
+/* Releases the context and its device memory (waits for its work). */
+sq_status sq_destroy(sq_ctx *ctx);
+
+const char *sq_last_error(void);
+
+sq_status sq_get_info(const sq_ctx *ctx, sq_info *info);
+
+/* Forward pass: Section 2.2 scaling, Eq. (Chebyshev) recurrence on every node
+ * region, moments mu_k^q and their sum M_k = sum_q mu_k^q (the per-process
+ * sum before the global reduction of Eq. (Ne)).
+ *   V            device, FP64, the local potential on V's grid (read only).
+ *   lambda_min,
+ *   lambda_max   spectral bounds of the whole-domain H used for the scaling
+ *                omega = (max+min)/2, tau = (max-min)/2; pass NaN, NaN to
+ *                estimate them on the device (FP64 Lanczos on the whole-domain
+ *                H, widened by 1% of the width on each side).
+ *   moments      device [n_nodes][K+1] FP64 output, or NULL (kept internally).
+ *   moment_sum   device [K+1] FP64 output, or NULL.
+ *   stream       hipStream_t.
+ * The context keeps the scaled diagonal and the bounds for sq_fermi_level and
+ * sq_density_backward. */
+sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lambda_max,
+                     double *moments, double *moment_sum, void *stream);
+
+/* Fermi level and pointwise fields, Eqs. (Ne), (rhoq), (uq).
+ * Bisection on [lambda_min, lambda_max] for N_e(lambda_f) = Ne_target with
+ * N_e = 2 (c_0 M_0/2 + sum_k c_k M_k); mid = lo + (hi-lo)/2, lo = mid when
+ * N_e(mid) < target, stop when |N_e(mid) - target| < tol_Ne or the bracket
+ * is below 4 eps.  max_iter == 0 skips the solve and uses *lambda_f as given.
+ *   lambda_f  device scalar FP64: output (input when max_iter == 0).
+ *   rho, u    device [n_nodes] FP64 outputs (electrons per node and band
+ *             energy per node), or NULL.
+ *   totals    device [8] FP64 output: {N_e, U, dN_e/dlambda_f, dU/dlambda_f,
+ *             omega, tau, iterations, status} with status 0 or SQ_ERR_*.
+ * Requires a preceding sq_density on the same context. */
+sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
+                         double *lambda_f, double *rho, double *u, double *totals,
+                         void *stream);
+
+/* Adjoint (reverse mode) of the forward pass at fixed lambda_f, omega, tau:
+ * for y = sum_q (g_rho[q] rho^q + g_u[q] u^q) accumulates
+ *   dV[x] += dy/dV(x)          (V's grid, FP64)
+ *   dR[J] += dy/dR_J           ([n_atoms][3] FP64, gradient through chi(x - R_J);
+ *                                the nonlocal force is its negative)
+ * by the reverse Chebyshev recurrence with checkpoints every ckpt_every steps.
+ *   g_rho, g_u  device [n_nodes] FP64 cotangents (either may be NULL = 0).
+ *   dV          device, accumulated (+=), or NULL.
+ *   dR          device, accumulated (+=), or NULL; needs dchi at setup.
+ * Requires sq_density and sq_fermi_level on the same context before it. */
+sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_u, double *dV,
+                              double *dR, void *stream);
+
+/* Synchronises the context's last stream and returns the device-side status
+ * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */
+sq_status sq_device_status(sq_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQ_H */

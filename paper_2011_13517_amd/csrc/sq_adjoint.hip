@@ -1,0 +1,39 @@
+// Adjoint dispatch over the FD radius; the kernels live in sq_adjoint_kernel.h
+// and are instantiated per radius in sq_adjoint_r<R>.hip.
+#include "sq_internal.h"
+
+namespace sqk {
+
+template <int R>
+hipError_t adjoint_dispatch_r(int prec, int E, bool M, bool G, const void *args, int grid,
+                              hipStream_t s, int *occ);
+
+static hipError_t dispatch(int prec, int E, int R, bool M, bool G, const void *args, int grid,
+                           hipStream_t s, int *occ) {
+    switch (R) {
+        case 1: return adjoint_dispatch_r<1>(prec, E, M, G, args, grid, s, occ);
+        case 2: return adjoint_dispatch_r<2>(prec, E, M, G, args, grid, s, occ);
+        case 3: return adjoint_dispatch_r<3>(prec, E, M, G, args, grid, s, occ);
+        case 4: return adjoint_dispatch_r<4>(prec, E, M, G, args, grid, s, occ);
+        case 5: return adjoint_dispatch_r<5>(prec, E, M, G, args, grid, s, occ);
+        case 6: return adjoint_dispatch_r<6>(prec, E, M, G, args, grid, s, occ);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// FP32 adjoint up to edge 27, FP64 adjoint up to edge 21 (LDS holds the box
+// plus the per-atom projection tables).
+int adjoint_max_edge(int prec) { return prec == SQ_FP64 ? 21 : 27; }
+
+hipError_t launch_adjoint(int prec, int E, int R, bool maskz, bool grad, const void *args,
+                          int grid, hipStream_t s) {
+    return dispatch(prec, E, R, maskz, grad, args, grid, s, nullptr);
+}
+
+int adjoint_blocks_per_cu(int prec, int E, int R, bool maskz, bool grad) {
+    int occ = 1;
+    dispatch(prec, E, R, maskz, grad, nullptr, 0, nullptr, &occ);
+    return occ;
+}
+
+}  // namespace sqk

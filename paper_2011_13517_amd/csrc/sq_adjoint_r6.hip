@@ -1,0 +1,7 @@
+// Adjoint kernels for FD radius 6 (split out so the instantiations build in parallel).
+#include "sq_adjoint_kernel.h"
+
+namespace sqk {
+template hipError_t adjoint_dispatch_r<6>(int, int, bool, bool, const void *, int, hipStream_t,
+                                           int *);
+}  // namespace sqk

@@ -1,0 +1,722 @@
+// C ABI of libsq: context setup (work list, projector tables, workspaces) and
+// the host side of sq_density / sq_fermi_level / sq_density_backward.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sq_kernels.h"
+
+using namespace sqk;
+
+namespace {
+
+thread_local std::string g_err;
+
+sq_status fail(sq_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SQ_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr int LANCZOS_STEPS = 100;
+constexpr double LANCZOS_MARGIN = 0.01;
+constexpr uint64_t LANCZOS_SEED = 0x5EEDULL;
+constexpr int NQ_CAP_LOG2 = 22;
+#ifndef SQ_N_PARTIAL
+#define SQ_N_PARTIAL 512   // blocks of the deterministic grid reductions
+#endif
+constexpr int N_PARTIAL = SQ_N_PARTIAL;
+
+// central second-derivative weights of radius r (the paper's FD Laplacian,
+// Section 3): w_p = 2 (-1)^{p+1} (r!)^2 / (p^2 (r-p)! (r+p)!), w_0 = -2 sum w_p
+void fd_weights(int r, double *w) {
+    double s = 0.0;
+    for (int p = 1; p <= r; ++p) {
+        double f = 1.0;
+        for (int j = 1; j <= p; ++j) f *= double(r - p + j) / double(r + j);
+        w[p] = ((p % 2) ? 2.0 : -2.0) * f / double(p * p);
+        s += w[p];
+    }
+    w[0] = -2.0 * s;
+}
+
+}  // namespace
+
+struct sq_ctx {
+    sq_params p{};
+    int r = 1;
+    double w[MAX_R + 1] = {};
+    double ih2[3] = {}, kin = 0, h3 = 0;
+    int N[3] = {};
+    int64_t nv = 0;
+    int periodic = 0;
+    int64_t n_nodes = 0;
+    int K = 0;
+    int prec = 0;
+    int aprec = 0;   // precision of the adjoint
+    int E = 0;
+    bool maskz = false;
+    int grid_fwd = 1;
+    int max_region[3] = {};
+    int64_t region_points = 0;
+    int64_t bytes = 0;
+    // device
+    std::vector<void *> allocs;
+    Item *d_items = nullptr;
+    int n_items = 0;
+    int32_t *d_counter = nullptr;
+    int32_t *d_status = nullptr;
+    Scalars *d_scal = nullptr;
+    float *d_D32 = nullptr;
+    double *d_D64 = nullptr;
+    double *d_mu = nullptr;       // internal moments
+    const double *mu_last = nullptr;
+    double *d_M = nullptr;
+    double *d_mpartial = nullptr;
+    int n_mpart = 0;
+    // projectors
+    int n_atoms = 0, n_proj = 0;
+    bool have_dchi = false;
+    AtomDev *d_atoms = nullptr;
+    int32_t *d_pack = nullptr;
+    float *d_chi32 = nullptr, *d_dchi32 = nullptr;
+    double *d_chi64 = nullptr, *d_dchi64 = nullptr;
+    double *d_cJ = nullptr;
+    int64_t *d_sup_off = nullptr, *d_sup_idx = nullptr;
+    int64_t n_upts = 0;
+    int64_t *d_pt_idx = nullptr, *d_pt_off = nullptr, *d_pt_row = nullptr;
+    int32_t *d_pt_atom = nullptr;
+    LanczosWork lz{};
+    FermiWork fw{};
+    // adjoint
+    bool adj_ok = false;
+    int grid_adj = 1;
+    int n_ckpt = 1;
+    int64_t ckpt_stride = 0;
+    void *d_ckpt = nullptr;
+    bool have_density = false, have_fermi = false;
+    hipStream_t last_stream = nullptr;
+
+    template <typename T>
+    sq_status alloc(T **ptr, size_t n) {
+        *ptr = nullptr;
+        if (n == 0) n = 1;
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, n * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SQ_ERR_OOM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T),
+                        hipGetErrorString(e));
+        }
+        allocs.push_back(q);
+        bytes += (int64_t)(n * sizeof(T));
+        *ptr = static_cast<T *>(q);
+        return SQ_OK;
+    }
+    template <typename T>
+    sq_status upload(T **ptr, const T *src, size_t n) {
+        sq_status st = alloc(ptr, n);
+        if (st) return st;
+        if (n) {
+            const hipError_t e = hipMemcpy(*ptr, src, n * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(SQ_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+        }
+        return SQ_OK;
+    }
+    ~sq_ctx() {
+        for (void *q : allocs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+#define TRY(expr)                    \
+    do {                             \
+        sq_status s_ = (expr);       \
+        if (s_ != SQ_OK) return s_;  \
+    } while (0)
+
+sq_status validate(const sq_params *p) {
+    if (!p) return fail(SQ_ERR_ARG, "params is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (p->n[a] < 1) return fail(SQ_ERR_ARG, "n[%d] = %d must be >= 1", a, p->n[a]);
+        if (!(p->h[a] > 0.0)) return fail(SQ_ERR_ARG, "h[%d] must be > 0", a);
+        if (p->rcut[a] < 0) return fail(SQ_ERR_ARG, "rcut[%d] must be >= 0", a);
+    }
+    if (p->fd_order < 2 || p->fd_order > 2 * MAX_R || p->fd_order % 2)
+        return fail(SQ_ERR_ARG, "fd_order %d must be even in [2, %d]", p->fd_order, 2 * MAX_R);
+    if (p->bc < 0 || p->bc > 2) return fail(SQ_ERR_ARG, "bc %d unknown", p->bc);
+    if (p->order < 1 || p->order > 512) return fail(SQ_ERR_ARG, "order %d not in [1, 512]", p->order);
+    if (!(p->kT > 0.0)) return fail(SQ_ERR_ARG, "kT must be > 0");
+    if (p->precision != SQ_FP64 && p->precision != SQ_FP32_ACC64)
+        return fail(SQ_ERR_ARG, "precision %d unknown", p->precision);
+    if (p->ckpt_every < 0) return fail(SQ_ERR_ARG, "ckpt_every must be >= 0");
+    if (p->adjoint_precision != SQ_FP64 && p->adjoint_precision != SQ_FP32_ACC64)
+        return fail(SQ_ERR_ARG, "adjoint_precision %d unknown", p->adjoint_precision);
+    return SQ_OK;
+}
+
+// unwrapped bounding box of a set of coordinates on a ring of n cells
+void ring_bbox(std::vector<int> &c, int n, bool periodic, int *lo, int *dim) {
+    if (!periodic) {
+        const auto mm = std::minmax_element(c.begin(), c.end());
+        *lo = *mm.first;
+        *dim = *mm.second - *mm.first + 1;
+        return;
+    }
+    std::vector<char> occ(n, 0);
+    for (int x : c) occ[x] = 1;
+    // the support starts right after the longest circular run of empty cells
+    int best_len = -1, best_end = 0;
+    for (int s = 0; s < n; ++s) {
+        if (occ[s] || !occ[(s + n - 1) % n]) continue;   // not the start of an empty run
+        int len = 0;
+        while (len < n && !occ[(s + len) % n]) ++len;
+        if (len > best_len) {
+            best_len = len;
+            best_end = (s + len) % n;
+        }
+    }
+    if (best_len <= 0) {   // fills the ring
+        *lo = 0;
+        *dim = n;
+        return;
+    }
+    *lo = best_end;
+    int mx = 0;
+    for (int x : c) mx = std::max(mx, ((x - best_end) % n + n) % n);
+    *dim = mx + 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sq_last_error(void) { return g_err.c_str(); }
+
+sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int64_t *nodes,
+                   const int32_t *node_rcut, int64_t n_nodes, sq_ctx **out) {
+    if (!out) return fail(SQ_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    TRY(validate(params));
+    auto ctx = new (std::nothrow) sq_ctx;
+    if (!ctx) return fail(SQ_ERR_OOM, "host allocation failed");
+    sq_ctx &c = *ctx;
+    auto bail = [&](sq_status st) {
+        delete ctx;
+        return st;
+    };
+    c.p = *params;
+    if (c.p.ckpt_every == 0) c.p.ckpt_every = 10;
+    c.r = c.p.fd_order / 2;
+    fd_weights(c.r, c.w);
+    c.kin = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        c.ih2[a] = 1.0 / (c.p.h[a] * c.p.h[a]);
+        c.kin += -0.5 * c.w[0] * c.ih2[a];
+    }
+    c.h3 = c.p.h[0] * c.p.h[1] * c.p.h[2];
+    c.periodic = c.p.bc == SQ_BC_PERIODIC;
+    int pad[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        if (c.p.bc == SQ_BC_EMBEDDED) pad[a] = c.p.rcut[a];
+        c.N[a] = c.p.n[a] + 2 * pad[a];
+    }
+    c.nv = (int64_t)c.N[0] * c.N[1] * c.N[2];
+    c.K = c.p.order;
+    c.prec = c.p.precision;
+    c.aprec = c.p.adjoint_precision;
+    const int64_t n_omega = (int64_t)c.p.n[0] * c.p.n[1] * c.p.n[2];
+    if (!nodes) {
+        if (n_nodes != n_omega)
+            return bail(fail(SQ_ERR_ARG, "nodes == NULL needs n_nodes == %lld", (long long)n_omega));
+    } else if (n_nodes < 1) {
+        return bail(fail(SQ_ERR_ARG, "n_nodes must be >= 1"));
+    }
+    if (n_nodes > INT32_MAX) return bail(fail(SQ_ERR_ARG, "too many nodes"));
+    c.n_nodes = n_nodes;
+
+    // ---- work list -------------------------------------------------------
+    std::vector<Item> items(n_nodes);
+    int emax = 0;
+    for (int64_t q = 0; q < n_nodes; ++q) {
+        const int64_t g = nodes ? nodes[q] : q;
+        if (g < 0 || g >= n_omega)
+            return bail(fail(SQ_ERR_ARG, "node %lld out of range", (long long)g));
+        const int pos[3] = {(int)(g % c.p.n[0]), (int)((g / c.p.n[0]) % c.p.n[1]),
+                            (int)(g / ((int64_t)c.p.n[0] * c.p.n[1]))};
+        Item &it = items[q];
+        it.out = (int32_t)q;
+        for (int a = 0; a < 3; ++a) {
+            const int m = node_rcut ? node_rcut[3 * q + a] : c.p.rcut[a];
+            if (m < 0) return bail(fail(SQ_ERR_ARG, "node_rcut must be >= 0"));
+            if (c.p.bc == SQ_BC_PERIODIC) {
+                if (2 * m + 1 + c.r > c.p.n[a])
+                    return bail(fail(SQ_ERR_ARG,
+                                     "periodic region of half-width %d overlaps itself on axis %d "
+                                     "(needs 2*rcut+1+r <= n)", m, a));
+                it.lo[a] = pos[a] - m;
+                it.dim[a] = 2 * m + 1;
+                it.ctr[a] = m;
+            } else if (c.p.bc == SQ_BC_DIRICHLET) {
+                const int l = std::max(pos[a] - m, 0), u = std::min(pos[a] + m, c.p.n[a] - 1);
+                it.lo[a] = l;
+                it.dim[a] = u - l + 1;
+                it.ctr[a] = pos[a] - l;
+            } else {
+                if (m > pad[a])
+                    return bail(fail(SQ_ERR_ARG, "embedded node half-width %d exceeds the padding "
+                                     "%d", m, pad[a]));
+                it.lo[a] = pos[a] + pad[a] - m;
+                it.dim[a] = 2 * m + 1;
+                it.ctr[a] = m;
+            }
+            emax = std::max(emax, it.dim[a]);
+            c.max_region[a] = std::max(c.max_region[a], it.dim[a]);
+        }
+        c.region_points += (int64_t)it.dim[0] * it.dim[1] * it.dim[2];
+    }
+    if (emax > max_edge(c.prec))
+        return bail(fail(SQ_ERR_ARG, "region edge %d exceeds the supported %d for this precision",
+                         emax, max_edge(c.prec)));
+    c.E = edge_bucket(emax);
+    c.maskz = false;
+    bool uniform = true;
+    for (const Item &it : items) {
+        if (it.dim[2] != c.E) c.maskz = true;
+        if (it.dim[0] != items[0].dim[0] || it.dim[1] != items[0].dim[1] ||
+            it.dim[2] != items[0].dim[2])
+            uniform = false;
+    }
+    if (!uniform) {   // largest regions first (longest-processing-time order)
+        std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+            return (int64_t)a.dim[0] * a.dim[1] * a.dim[2] > (int64_t)b.dim[0] * b.dim[1] * b.dim[2];
+        });
+    }
+    c.n_items = (int)n_nodes;
+
+    // ---- projectors ------------------------------------------------------
+    std::vector<AtomDev> atoms;
+    std::vector<int32_t> pack;
+    std::vector<double> chi64, dchi64, cJ;
+    std::vector<int64_t> sup_off, sup_idx;
+    if (proj && proj->n_atoms > 0) {
+        if (proj->n_proj < 1 || proj->n_proj > NP)
+            return bail(fail(SQ_ERR_ARG, "n_proj %d not in [1, %d]", proj->n_proj, NP));
+        if (!proj->sup_off || !proj->sup_idx || !proj->chi || !proj->c)
+            return bail(fail(SQ_ERR_ARG, "projector tables incomplete"));
+        c.n_atoms = proj->n_atoms;
+        c.n_proj = proj->n_proj;
+        c.have_dchi = proj->dchi != nullptr;
+        const int np = proj->n_proj;
+        const int64_t nnz = proj->sup_off[proj->n_atoms];
+        if (proj->sup_off[0] != 0 || nnz < 0 || nnz > INT32_MAX)
+            return bail(fail(SQ_ERR_ARG, "bad sup_off"));
+        atoms.resize(c.n_atoms);
+        pack.resize(nnz);
+        chi64.assign(nnz * NP, 0.0);
+        dchi64.assign(nnz * NP * 3, 0.0);
+        cJ.assign((size_t)c.n_atoms * NP, 0.0);
+        sup_off.assign(proj->sup_off, proj->sup_off + c.n_atoms + 1);
+        sup_idx.assign(proj->sup_idx, proj->sup_idx + nnz);
+        int bbmax[3] = {0, 0, 0};
+        std::vector<int> cc[3];
+        for (int J = 0; J < c.n_atoms; ++J) {
+            const int64_t s0 = proj->sup_off[J], s1 = proj->sup_off[J + 1];
+            if (s1 < s0) return bail(fail(SQ_ERR_ARG, "sup_off not monotone"));
+            for (int l = 0; l < np; ++l) cJ[(size_t)J * NP + l] = proj->c[(int64_t)J * np + l];
+            AtomDev &at = atoms[J];
+            at.start = (int32_t)s0;
+            at.count = (int32_t)(s1 - s0);
+            if (s1 == s0) {
+                for (int a = 0; a < 3; ++a) { at.lo[a] = 0; at.dim[a] = 0; }
+                continue;
+            }
+            for (int a = 0; a < 3; ++a) cc[a].clear();
+            for (int64_t s = s0; s < s1; ++s) {
+                const int64_t g = proj->sup_idx[s];
+                if (g < 0 || g >= c.nv)
+                    return bail(fail(SQ_ERR_ARG, "support index %lld out of range", (long long)g));
+                cc[0].push_back((int)(g % c.N[0]));
+                cc[1].push_back((int)((g / c.N[0]) % c.N[1]));
+                cc[2].push_back((int)(g / ((int64_t)c.N[0] * c.N[1])));
+            }
+            for (int a = 0; a < 3; ++a) {
+                ring_bbox(cc[a], c.N[a], c.periodic != 0, &at.lo[a], &at.dim[a]);
+                if (at.dim[a] > 1023)
+                    return bail(fail(SQ_ERR_ARG, "projector support too wide (%d nodes)", at.dim[a]));
+                bbmax[a] = std::max(bbmax[a], at.dim[a]);
+            }
+            for (int64_t s = s0; s < s1; ++s) {
+                int o[3];
+                for (int a = 0; a < 3; ++a) {
+                    int x = cc[a][s - s0] - at.lo[a];
+                    if (c.periodic) x = ((x % c.N[a]) + c.N[a]) % c.N[a];
+                    o[a] = x;
+                }
+                pack[s] = o[0] | (o[1] << 10) | (o[2] << 20);
+                for (int l = 0; l < np; ++l) {
+                    chi64[s * NP + l] = proj->chi[s * np + l];
+                    if (proj->dchi)
+                        for (int x = 0; x < 3; ++x)
+                            dchi64[(s * NP + l) * 3 + x] = proj->dchi[(s * np + l) * 3 + x];
+                }
+            }
+        }
+        if (c.periodic)
+            for (int a = 0; a < 3; ++a)
+                if (c.max_region[a] + bbmax[a] > c.N[a])
+                    return bail(fail(SQ_ERR_ARG, "region + projector support (%d + %d) exceeds the "
+                                     "periodic grid (%d) on axis %d", c.max_region[a], bbmax[a],
+                                     c.N[a], a));
+    }
+
+    // ---- device memory ---------------------------------------------------
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return bail(fail(SQ_ERR_HIP, "no HIP device"));
+    const int64_t K1 = c.K + 1;
+    sq_status st;
+#define ALLOC(ptr, n)                                              \
+    do {                                                           \
+        if ((st = c.alloc(&(ptr), (n))) != SQ_OK) return bail(st); \
+    } while (0)
+#define UPLOAD(ptr, src, n)                                                 \
+    do {                                                                    \
+        if ((st = c.upload(&(ptr), (src), (n))) != SQ_OK) return bail(st);  \
+    } while (0)
+    UPLOAD(c.d_items, items.data(), items.size());
+    ALLOC(c.d_counter, 4);
+    ALLOC(c.d_status, 4);
+    ALLOC(c.d_scal, 1);
+    if (c.prec == SQ_FP64 || c.aprec == SQ_FP64) ALLOC(c.d_D64, c.nv);
+    if (c.prec == SQ_FP32_ACC64 || c.aprec == SQ_FP32_ACC64) ALLOC(c.d_D32, c.nv);
+    ALLOC(c.d_mu, (size_t)(n_nodes * K1));
+    ALLOC(c.d_M, K1);
+    c.n_mpart = (int)std::min<int64_t>(N_PARTIAL, n_nodes);
+    ALLOC(c.d_mpartial, (size_t)c.n_mpart * K1);
+    if (c.n_atoms) {
+        UPLOAD(c.d_atoms, atoms.data(), atoms.size());
+        UPLOAD(c.d_pack, pack.data(), pack.size());
+        UPLOAD(c.d_chi64, chi64.data(), chi64.size());
+        UPLOAD(c.d_cJ, cJ.data(), cJ.size());
+        UPLOAD(c.d_sup_off, sup_off.data(), sup_off.size());
+        UPLOAD(c.d_sup_idx, sup_idx.data(), sup_idx.size());
+        if (c.have_dchi) UPLOAD(c.d_dchi64, dchi64.data(), dchi64.size());
+        if (c.prec == SQ_FP32_ACC64 || c.aprec == SQ_FP32_ACC64) {
+            std::vector<float> f(chi64.begin(), chi64.end());
+            UPLOAD(c.d_chi32, f.data(), f.size());
+            if (c.have_dchi) {
+                std::vector<float> g(dchi64.begin(), dchi64.end());
+                UPLOAD(c.d_dchi32, g.data(), g.size());
+            }
+        }
+        // point-major view for the whole-domain operator
+        const int64_t nnz = (int64_t)sup_idx.size();
+        std::vector<int64_t> order(nnz);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return sup_idx[a] < sup_idx[b]; });
+        std::vector<int64_t> pt_idx, pt_off, pt_row(nnz);
+        std::vector<int32_t> pt_atom(nnz);
+        std::vector<int32_t> atom_of(nnz);
+        for (int J = 0; J < c.n_atoms; ++J)
+            for (int64_t s = sup_off[J]; s < sup_off[J + 1]; ++s) atom_of[s] = J;
+        for (int64_t e = 0; e < nnz; ++e) {
+            const int64_t row = order[e];
+            if (e == 0 || sup_idx[row] != sup_idx[order[e - 1]]) {
+                pt_idx.push_back(sup_idx[row]);
+                pt_off.push_back(e);
+            }
+            pt_row[e] = row;
+            pt_atom[e] = atom_of[row];
+        }
+        pt_off.push_back(nnz);
+        c.n_upts = (int64_t)pt_idx.size();
+        UPLOAD(c.d_pt_idx, pt_idx.data(), pt_idx.size());
+        UPLOAD(c.d_pt_off, pt_off.data(), pt_off.size());
+        UPLOAD(c.d_pt_row, pt_row.data(), pt_row.size());
+        UPLOAD(c.d_pt_atom, pt_atom.data(), pt_atom.size());
+    }
+    // Lanczos and Fermi workspaces
+    ALLOC(c.lz.q, c.nv);
+    ALLOC(c.lz.qp, c.nv);
+    ALLOC(c.lz.y, c.nv);
+    ALLOC(c.lz.alpha, LANCZOS_STEPS);
+    ALLOC(c.lz.beta, LANCZOS_STEPS);
+    ALLOC(c.lz.partial, N_PARTIAL);
+    ALLOC(c.lz.partial2, N_PARTIAL);
+    ALLOC(c.lz.cp, (size_t)std::max(1, c.n_atoms) * NP);
+    c.lz.n_partial = N_PARTIAL;
+    ALLOC(c.fw.P, (size_t)1 << NQ_CAP_LOG2);
+    ALLOC(c.fw.partial, N_PARTIAL);
+    ALLOC(c.fw.ticket, 1);
+    ALLOC(c.fw.cp, K1);
+    ALLOC(c.fw.dp, K1);
+    ALLOC(c.fw.dcp, K1);
+    ALLOC(c.fw.dup, K1);
+    c.fw.n_partial = N_PARTIAL;
+    c.fw.nq_cap_log2 = NQ_CAP_LOG2;
+    if (hipMemset(c.fw.ticket, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(c.d_status, 0, sizeof(int32_t)) != hipSuccess ||
+        hipMemset(c.d_scal, 0, sizeof(Scalars)) != hipSuccess)
+        return bail(fail(SQ_ERR_HIP, "hipMemset failed"));
+    const int occ = forward_blocks_per_cu(c.prec, c.E, c.r, c.maskz);
+    c.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, c.n_items));
+    // adjoint: one checkpoint slot of ceil((K-1)/C) box pairs per resident workgroup
+    c.adj_ok = c.E <= adjoint_max_edge(c.aprec);
+    if (c.adj_ok) {
+        const bool grad = c.n_atoms > 0 && c.have_dchi;
+        const int aocc = adjoint_blocks_per_cu(c.aprec, c.E, c.r, c.maskz, grad);
+        c.grid_adj = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)aocc * ncu, c.n_items));
+        c.n_ckpt = c.K >= 2 ? (c.K - 2) / c.p.ckpt_every + 1 : 1;
+        const int64_t e3 = (int64_t)c.E * c.E * c.E;
+        c.ckpt_stride = (int64_t)c.n_ckpt * 2 * e3;
+        const size_t n = (size_t)c.grid_adj * c.ckpt_stride;
+        if (c.aprec == SQ_FP64) {
+            double *q = nullptr;
+            ALLOC(q, n);
+            c.d_ckpt = q;
+        } else {
+            float *q = nullptr;
+            ALLOC(q, n);
+            c.d_ckpt = q;
+        }
+    }
+#undef ALLOC
+#undef UPLOAD
+    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(SQ_ERR_HIP, "setup sync failed"));
+    *out = ctx;
+    return SQ_OK;
+}
+
+sq_status sq_destroy(sq_ctx *ctx) {
+    if (!ctx) return SQ_OK;
+    (void)hipDeviceSynchronize();
+    delete ctx;
+    return SQ_OK;
+}
+
+sq_status sq_get_info(const sq_ctx *ctx, sq_info *info) {
+    if (!ctx || !info) return fail(SQ_ERR_ARG, "NULL argument");
+    info->n_nodes = ctx->n_nodes;
+    info->order = ctx->K;
+    for (int a = 0; a < 3; ++a) {
+        info->vgrid[a] = ctx->N[a];
+        info->max_region[a] = ctx->max_region[a];
+    }
+    info->n_atoms = ctx->n_atoms;
+    info->region_points = ctx->region_points;
+    info->workspace_bytes = ctx->bytes;
+    return SQ_OK;
+}
+
+sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lambda_max,
+                     double *moments, double *moment_sum, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    if (!V) return fail(SQ_ERR_ARG, "V is NULL");
+    sq_ctx &c = *ctx;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool estimate = std::isnan(lambda_min) && std::isnan(lambda_max);
+    if (!estimate && !(lambda_max > lambda_min && std::isfinite(lambda_min) &&
+                       std::isfinite(lambda_max)))
+        return fail(SQ_ERR_SPECTRUM, "need lambda_max > lambda_min (or both NaN)");
+    if (estimate) {
+        FullOp op{};
+        for (int a = 0; a < 3; ++a) {
+            op.N[a] = c.N[a];
+            op.ih2[a] = c.ih2[a];
+        }
+        op.periodic = c.periodic;
+        op.r = c.r;
+        for (int p = 0; p <= MAX_R; ++p) op.w[p] = c.w[p];
+        op.kin = c.kin;
+        op.h3 = c.h3;
+        op.V = V;
+        op.n_atoms = c.n_atoms;
+        op.sup_off = c.d_sup_off;
+        op.sup_idx = c.d_sup_idx;
+        op.chi = c.d_chi64;
+        op.cJ = c.d_cJ;
+        op.n_upts = c.n_upts;
+        op.pt_idx = c.d_pt_idx;
+        op.pt_off = c.d_pt_off;
+        op.pt_row = c.d_pt_row;
+        op.pt_atom = c.d_pt_atom;
+        HIP_TRY(k_lanczos_bounds(op, c.lz, LANCZOS_STEPS, LANCZOS_SEED, LANCZOS_MARGIN, c.d_scal, st));
+    } else {
+        HIP_TRY(k_set_bounds(c.d_scal, lambda_min, lambda_max, st));
+    }
+    HIP_TRY(k_build_diag(V, c.nv, c.kin, c.d_scal, c.d_D64, c.d_D32, st));
+    HIP_TRY(k_fill_i32(c.d_counter, 0, 1, st));
+    HIP_TRY(k_fill_i32(c.d_status, 0, 1, st));
+    double *mu = moments ? moments : c.d_mu;
+    if (c.prec == SQ_FP64) {
+        RegionArgs<double> a{};
+        a.items = c.d_items;
+        a.n_items = c.n_items;
+        a.counter = c.d_counter;
+        a.D = c.d_D64;
+        for (int x = 0; x < 3; ++x) { a.N[x] = c.N[x]; a.ih2[x] = c.ih2[x]; }
+        a.periodic = c.periodic;
+        a.scal = c.d_scal;
+        for (int p = 0; p <= MAX_R; ++p) a.w[p] = c.w[p];
+        a.h3 = c.h3;
+        a.K = c.K;
+        a.moments = mu;
+        a.n_atoms = c.n_atoms;
+        a.atoms = c.d_atoms;
+        a.sup_pack = c.d_pack;
+        a.chi = c.d_chi64;
+        a.dchi = c.d_dchi64;
+        a.cJ = c.d_cJ;
+        a.status = c.d_status;
+        HIP_TRY(launch_forward(c.prec, c.E, c.r, c.maskz, &a, c.grid_fwd, st));
+    } else {
+        RegionArgs<float> a{};
+        a.items = c.d_items;
+        a.n_items = c.n_items;
+        a.counter = c.d_counter;
+        a.D = c.d_D32;
+        for (int x = 0; x < 3; ++x) { a.N[x] = c.N[x]; a.ih2[x] = c.ih2[x]; }
+        a.periodic = c.periodic;
+        a.scal = c.d_scal;
+        for (int p = 0; p <= MAX_R; ++p) a.w[p] = c.w[p];
+        a.h3 = c.h3;
+        a.K = c.K;
+        a.moments = mu;
+        a.n_atoms = c.n_atoms;
+        a.atoms = c.d_atoms;
+        a.sup_pack = c.d_pack;
+        a.chi = c.d_chi32;
+        a.dchi = c.d_dchi32;
+        a.cJ = c.d_cJ;
+        a.status = c.d_status;
+        HIP_TRY(launch_forward(c.prec, c.E, c.r, c.maskz, &a, c.grid_fwd, st));
+    }
+    HIP_TRY(k_moment_sum(mu, c.n_nodes, c.K, c.d_mpartial, c.n_mpart, c.d_M, moment_sum, st));
+    c.mu_last = mu;
+    c.have_density = true;
+    c.have_fermi = false;
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
+                         double *lambda_f, double *rho, double *u, double *totals, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    sq_ctx &c = *ctx;
+    if (!c.have_density) return fail(SQ_ERR_STATE, "sq_fermi_level needs a preceding sq_density");
+    if (!lambda_f) return fail(SQ_ERR_ARG, "lambda_f is NULL");
+    if (max_iter < 0 || max_iter > 100000) return fail(SQ_ERR_ARG, "max_iter out of range");
+    if (max_iter > 0 && !(tol_Ne >= 0.0)) return fail(SQ_ERR_ARG, "tol_Ne must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(k_fermi(c.fw, c.d_scal, c.d_M, c.K, c.p.kT, Ne_target, tol_Ne, max_iter, lambda_f, st));
+    HIP_TRY(k_totals(c.fw, c.d_M, c.K, c.d_scal, totals, lambda_f, st));
+    if (rho || u) HIP_TRY(k_contract(c.mu_last, c.n_nodes, c.K, c.fw.cp, c.fw.dp, rho, u, st));
+    c.have_fermi = true;
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_u, double *dV,
+                              double *dR, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    sq_ctx &c = *ctx;
+    if (!c.have_fermi)
+        return fail(SQ_ERR_STATE, "sq_density_backward needs sq_density and sq_fermi_level first");
+    if (!c.adj_ok)
+        return fail(SQ_ERR_ARG, "the %s adjoint supports region edges up to %d (this context: %d)",
+                    c.aprec == SQ_FP64 ? "FP64" : "FP32", adjoint_max_edge(c.aprec), c.E);
+    if (dR && !(c.n_atoms > 0 && c.have_dchi))
+        return fail(SQ_ERR_ARG, "dR needs projector tables with dchi");
+    if (!dV && !dR) return SQ_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool grad = dR != nullptr;
+    HIP_TRY(k_fill_i32(c.d_counter, 0, 1, st));
+    auto fill = [&](auto &g) {
+        g.items = c.d_items;
+        g.n_items = c.n_items;
+        g.counter = c.d_counter;
+        for (int x = 0; x < 3; ++x) { g.N[x] = c.N[x]; g.ih2[x] = c.ih2[x]; }
+        g.periodic = c.periodic;
+        g.scal = c.d_scal;
+        for (int p = 0; p <= MAX_R; ++p) g.w[p] = c.w[p];
+        g.h3 = c.h3;
+        g.K = c.K;
+        g.moments = nullptr;
+        g.n_atoms = c.n_atoms;
+        g.atoms = c.d_atoms;
+        g.sup_pack = c.d_pack;
+        g.cJ = c.d_cJ;
+        g.status = c.d_status;
+    };
+    if (c.aprec == SQ_FP64) {
+        AdjointArgs<double> a{};
+        fill(a.g);
+        a.g.D = c.d_D64;
+        a.g.chi = c.d_chi64;
+        a.g.dchi = c.d_dchi64;
+        a.coef_c = c.fw.cp;
+        a.coef_d = c.fw.dp;
+        a.g_rho = g_rho;
+        a.g_u = g_u;
+        a.dV = dV;
+        a.dR = dR;
+        a.ckpt = static_cast<double *>(c.d_ckpt);
+        a.ckpt_every = c.p.ckpt_every;
+        a.n_ckpt = c.n_ckpt;
+        a.ckpt_stride = c.ckpt_stride;
+        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.maskz, grad, &a, c.grid_adj, st));
+    } else {
+        AdjointArgs<float> a{};
+        fill(a.g);
+        a.g.D = c.d_D32;
+        a.g.chi = c.d_chi32;
+        a.g.dchi = c.d_dchi32;
+        a.coef_c = c.fw.cp;
+        a.coef_d = c.fw.dp;
+        a.g_rho = g_rho;
+        a.g_u = g_u;
+        a.dV = dV;
+        a.dR = dR;
+        a.ckpt = static_cast<float *>(c.d_ckpt);
+        a.ckpt_every = c.p.ckpt_every;
+        a.n_ckpt = c.n_ckpt;
+        a.ckpt_stride = c.ckpt_stride;
+        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.maskz, grad, &a, c.grid_adj, st));
+    }
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_device_status(sq_ctx *ctx) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+    int32_t flag = 0;
+    Scalars s{};
+    HIP_TRY(hipMemcpy(&flag, ctx->d_status, sizeof(flag), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&s, ctx->d_scal, sizeof(s), hipMemcpyDeviceToHost));
+    if (flag) return fail(SQ_ERR_ARG, "a region touched more atoms than the kernel's atom table holds");
+    if (s.status) return fail((sq_status)s.status, "device reported status %d", s.status);
+    return SQ_OK;
+}
+
+}  // extern "C"

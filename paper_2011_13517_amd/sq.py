@@ -1,0 +1,134 @@
+"""Torch-facing wrapper of libsq: device tensors in, device tensors out.
+
+PyTorch only provides device memory and the current HIP stream; every step of
+the spectral-quadrature path runs in the HIP library behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .synth import Problem
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype=torch.float64):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
+    return t
+
+
+class Context:
+    """A spectral-quadrature context for one problem geometry (sq_setup)."""
+
+    def __init__(self, prob: Problem, precision: Optional[int] = None, nodes=None,
+                 node_rcut=None, ckpt_every: int = 0, adjoint_precision: int = L.SQ_FP64):
+        p = L.sq_params()
+        p.n[:] = [int(x) for x in prob.n]
+        p.h[:] = [float(x) for x in prob.h]
+        p.fd_order = int(prob.fd_order)
+        p.bc = int(prob.bc)
+        p.rcut[:] = [int(x) for x in prob.rcut]
+        p.order = int(prob.order)
+        p.kT = float(prob.kT)
+        p.precision = int(prob.precision if precision is None else precision)
+        p.ckpt_every = int(ckpt_every)
+        p.adjoint_precision = int(adjoint_precision)
+        self.params = p
+        self.prob = prob
+        self._keep = []
+        proj = None
+        if prob.n_atoms:
+            def arr(x, dt):
+                y = np.ascontiguousarray(x, dtype=dt)
+                self._keep.append(y)
+                return y.ctypes.data
+
+            proj = L.sq_projectors()
+            proj.n_atoms = int(prob.n_atoms)
+            proj.n_proj = int(prob.n_proj)
+            proj.sup_off = arr(prob.sup_off, np.int64)
+            proj.sup_idx = arr(prob.sup_idx, np.int64)
+            proj.chi = arr(prob.chi, np.float64)
+            proj.dchi = arr(prob.dchi, np.float64) if prob.dchi is not None else None
+            proj.c = arr(prob.c, np.float64)
+        if nodes is None and prob.nodes is not None:
+            nodes, node_rcut = prob.nodes, prob.node_rcut
+        if nodes is not None:
+            nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+            n_nodes = nodes.size
+            nptr = C.c_void_p(nodes.ctypes.data)
+        else:
+            n_nodes = int(np.prod(prob.n))
+            nptr = None
+        rptr = None
+        if node_rcut is not None:
+            node_rcut = np.ascontiguousarray(node_rcut, dtype=np.int32)
+            rptr = C.c_void_p(node_rcut.ctypes.data)
+        self.ctx = L.sq_setup(p, proj, nptr, rptr, n_nodes)
+        self.info = L.sq_get_info(self.ctx)
+        self.n_nodes = int(self.info.n_nodes)
+        self.K = int(self.info.order)
+        self.n_atoms = int(self.info.n_atoms)
+        self._keep = []
+
+    # -- forward -------------------------------------------------------------
+    def density(self, V: torch.Tensor, lambda_min: float = math.nan,
+                lambda_max: float = math.nan, moments: Optional[torch.Tensor] = None,
+                moment_sum: Optional[torch.Tensor] = None):
+        """sq_density: moments [n_nodes, K+1] and their sum [K+1] (FP64, device)."""
+        _dev(V)
+        dev = V.device
+        if moments is None:
+            moments = torch.empty((self.n_nodes, self.K + 1), dtype=torch.float64, device=dev)
+        if moment_sum is None:
+            moment_sum = torch.empty(self.K + 1, dtype=torch.float64, device=dev)
+        L.sq_density(self.ctx, _ptr(V), float(lambda_min), float(lambda_max), _ptr(moments),
+                     _ptr(moment_sum), _stream())
+        return moments, moment_sum
+
+    def fermi_level(self, Ne: float = 0.0, tol: float = 1e-10, max_iter: int = 200,
+                    lambda_f: Optional[torch.Tensor] = None, want_fields: bool = True,
+                    device=None):
+        """sq_fermi_level: (lambda_f[1], rho[n], u[n], totals[8]) on the device."""
+        dev = device or torch.device("cuda")
+        if lambda_f is None:
+            lambda_f = torch.zeros(1, dtype=torch.float64, device=dev)
+        rho = torch.empty(self.n_nodes, dtype=torch.float64, device=dev) if want_fields else None
+        u = torch.empty(self.n_nodes, dtype=torch.float64, device=dev) if want_fields else None
+        totals = torch.empty(8, dtype=torch.float64, device=dev)
+        L.sq_fermi_level(self.ctx, float(Ne), float(tol), int(max_iter), _ptr(lambda_f),
+                         _ptr(rho), _ptr(u), _ptr(totals), _stream())
+        return lambda_f, rho, u, totals
+
+    def backward(self, g_rho: Optional[torch.Tensor], g_u: Optional[torch.Tensor],
+                 dV: Optional[torch.Tensor] = None, dR: Optional[torch.Tensor] = None):
+        """sq_density_backward: accumulates into dV (V grid) and dR [n_atoms, 3]."""
+        L.sq_density_backward(self.ctx, _ptr(g_rho), _ptr(g_u), _ptr(dV), _ptr(dR), _stream())
+        return dV, dR
+
+    def status(self):
+        return L.sq_device_status(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            L.sq_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports what include/sq.h declares; host-side
+argument validation fails with SQ_ERR_ARG before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2011_13517_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sq_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libsq.so is not built (run __graft_entry__.build())")
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _params(**kw):
+    p = L.sq_params()
+    p.n[:] = [8, 8, 8]
+    p.h[:] = [0.5, 0.5, 0.5]
+    p.fd_order = 4
+    p.bc = 0
+    p.rcut[:] = [2, 2, 2]
+    p.order = 10
+    p.kT = 0.1
+    p.precision = 0
+    p.ckpt_every = 0
+    for k, v in kw.items():
+        if isinstance(getattr(p, k), C.Array):
+            getattr(p, k)[:] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(fd_order=3), dict(fd_order=14), dict(order=0),
+                                dict(kT=0.0), dict(bc=7), dict(precision=5), dict(h=[0.5, 0, 0.5]),
+                                dict(n=[8, 0, 8]), dict(rcut=[-1, 2, 2])])
+def test_invalid_params_rejected(lib, kw):
+    ctx = C.c_void_p()
+    st = lib.sq_setup(C.byref(_params(**kw)), None, None, None, 512, C.byref(ctx))
+    assert st == L.SQ_ERR_ARG
+    assert ctx.value is None
+    assert len(L.sq_last_error()) > 0
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.sq_setup(None, None, None, None, 0, None) == L.SQ_ERR_ARG
+    assert lib.sq_density(None, None, 0.0, 1.0, None, None, None) == L.SQ_ERR_ARG
+    assert lib.sq_fermi_level(None, 1.0, 1e-8, 10, None, None, None, None, None) == L.SQ_ERR_ARG
+    assert lib.sq_density_backward(None, None, None, None, None, None) == L.SQ_ERR_ARG
+    assert lib.sq_get_info(None, None) == L.SQ_ERR_ARG
+    assert lib.sq_destroy(None) == L.SQ_OK
+
+
+def test_binding_raises_with_message(lib):
+    with pytest.raises(L.SQError) as e:
+        L.sq_setup(_params(order=0), None, None, None, 512)
+    assert e.value.status == L.SQ_ERR_ARG
+    assert "order" in str(e.value)
+
+
+def test_package_has_no_fallback_path():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2011_13517_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "sq_oracle" not in txt, f
