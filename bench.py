@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=1536)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -55,7 +55,8 @@ def main():
     dev = torch.device("cuda:0")
     prob = synth.config(args.config)
     log(f"workload {prob.name}: {prob.n_nodes} nodes, K={prob.order}, atoms={prob.n_atoms}")
-    ctx = sq.Context(prob, precision=1, adjoint_precision=1)
+    # adjoint keeps every v_k of its in-flight regions (ckpt_every = 1)
+    ctx = sq.Context(prob, precision=1, adjoint_precision=1, ckpt_every=1)
     info = ctx.info
     K = ctx.K
     n_nodes = ctx.n_nodes
@@ -113,10 +114,15 @@ def main():
     log(f"timed {args.steps} steps in {wall:.3f} s -> {value:.4e} node-steps/s; "
         f"N_e={tot[0]:.10f} lambda_f={lam_v.item():.10f} iters={int(tot[6])}")
 
-    # roofline of the two region kernels (VALU-bound: the region state stays on chip)
+    # roofline of the two region kernels.  Algorithmic flops of one application of
+    # w = 2 Hs v - u at one region point: 3r symmetric pairs (add + FMA) = 9r, the
+    # diagonal FMA and the recurrence FMA = 4 (the nonlocal term is not counted).
+    # Forward: K applications.  Adjoint (store-all): K-1 forward applications to
+    # store v_0..v_{K-1}, K-1 adjoint applications and K FMAs into dV.
     r = prob.fd_order // 2
-    flops_fwd = region_points * K * (9 * r + 2)           # stencil: 3r adds + 3r FMAs + 1 FMA
-    flops_bwd = region_points * K * (3 * (9 * r + 2) + 2)  # forward again, rebuild, adjoint, dV
+    f_app = 9 * r + 4
+    flops_fwd = region_points * K * f_app
+    flops_bwd = region_points * ((2 * K - 2) * f_app + 2 * K)
     t_fwd = float(np.mean(times["fwd"]))
     t_bwd = float(np.mean(times["bwd"]))
     rf = dict(bound="alu", achieved=flops_fwd / t_fwd / 1e12, peak=PEAK_FP32_VALU / 1e12,
@@ -125,10 +131,8 @@ def main():
               unit="TFLOP/s", traffic=None)
     for d in (rf, rb):
         d["frac"] = d["achieved"] / d["peak"]
+    rf["kernel"], rb["kernel"] = "cheb_forward_kernel", "cheb_adjoint_kernel"
     dominant, other = (rb, rf) if t_bwd >= t_fwd else (rf, rb)
-    dominant = dict(dominant, kernel="cheb_adjoint_kernel" if dominant is rb else
-                    "cheb_forward_kernel")
-    other = dict(other, kernel="cheb_forward_kernel" if dominant is rb else "cheb_adjoint_kernel")
 
     # accuracy against the FP64 oracle on sampled nodes
     extra = {}

@@ -73,7 +73,10 @@ typedef struct {
     int32_t order;       /* Chebyshev degree K, 1..512                              */
     double kT;           /* smearing in Ha (> 0)                                    */
     int32_t precision;   /* sq_precision                                            */
-    int32_t ckpt_every;  /* adjoint checkpoint stride in steps (0 -> 10)            */
+    int32_t ckpt_every;  /* adjoint: 1 = keep every v_k of the in-flight regions     */
+                         /* (no rebuild); C > 1 = checkpoint pairs every C steps and  */
+                         /* rebuild v_k backwards; 0 = 1 if that pool fits in 8 GiB,  */
+                         /* else 10                                                    */
     int32_t adjoint_precision;  /* sq_precision of sq_density_backward (default 0 =  */
                          /* SQ_FP64: the gradient sums cancel strongly, so FP32      */
                          /* vectors lose ~1e-4 relative at K ~ 80; FP64 adjoint      */
@@ -137,7 +140,9 @@ sq_status sq_get_info(const sq_ctx *ctx, sq_info *info);
  *                omega = (max+min)/2, tau = (max-min)/2; pass NaN, NaN to
  *                estimate them on the device (FP64 Lanczos on the whole-domain
  *                H, widened by 1% of the width on each side).
- *   moments      device [n_nodes][K+1] FP64 output, or NULL (kept internally).
+ *   moments      device [n_nodes][K+1] FP64 output, or NULL (kept internally);
+ *                a caller buffer must stay valid until the next sq_density on
+ *                this context, because sq_fermi_level contracts it.
  *   moment_sum   device [K+1] FP64 output, or NULL.
  *   stream       hipStream_t.
  * The context keeps the scaled diagonal and the bounds for sq_fermi_level and
@@ -165,7 +170,8 @@ sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t m
  *   dV[x] += dy/dV(x)          (V's grid, FP64)
  *   dR[J] += dy/dR_J           ([n_atoms][3] FP64, gradient through chi(x - R_J);
  *                                the nonlocal force is its negative)
- * by the reverse Chebyshev recurrence with checkpoints every ckpt_every steps.
+ * by the reverse Chebyshev recurrence; v_k comes back from stored vectors
+ * (ckpt_every = 1) or is rebuilt backwards from checkpoints (ckpt_every > 1).
  *   g_rho, g_u  device [n_nodes] FP64 cotangents (either may be NULL = 0).
  *   dV          device, accumulated (+=), or NULL.
  *   dR          device, accumulated (+=), or NULL; needs dchi at setup.

@@ -25,14 +25,14 @@ static hipError_t dispatch(int prec, int E, int R, bool M, bool G, const void *a
 // plus the per-atom projection tables).
 int adjoint_max_edge(int prec) { return prec == SQ_FP64 ? 21 : 27; }
 
-hipError_t launch_adjoint(int prec, int E, int R, bool maskz, bool grad, const void *args,
+hipError_t launch_adjoint(int prec, int E, int R, bool storeall, bool grad, const void *args,
                           int grid, hipStream_t s) {
-    return dispatch(prec, E, R, maskz, grad, args, grid, s, nullptr);
+    return dispatch(prec, E, R, storeall, grad, args, grid, s, nullptr);
 }
 
-int adjoint_blocks_per_cu(int prec, int E, int R, bool maskz, bool grad) {
+int adjoint_blocks_per_cu(int prec, int E, int R, bool storeall, bool grad) {
     int occ = 1;
-    dispatch(prec, E, R, maskz, grad, nullptr, 0, nullptr, &occ);
+    dispatch(prec, E, R, storeall, grad, nullptr, 0, nullptr, &occ);
     return occ;
 }
 

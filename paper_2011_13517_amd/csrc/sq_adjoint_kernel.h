@@ -38,26 +38,247 @@ __device__ __forceinline__ void dots_only(const RegionArgs<T> &a, const StepCtx<
     __syncthreads();
 }
 
-template <typename T, int E, int R, bool MASKZ, bool GRAD>
+// checkpoint slot I/O: layout [pair][which][z][pencil] so a wave's stores coalesce
+template <typename T, int E>
+__device__ __forceinline__ void ck_store(T *ck, bool active, int tid, int cidx, int which,
+                                         const T (&vec)[E]) {
+    if (!active) return;
+#pragma unroll
+    for (int z = 0; z < E; ++z) ck[((int64_t)(cidx * 2 + which) * E + z) * (E * E) + tid] = vec[z];
+}
+template <typename T, int E>
+__device__ __forceinline__ void ck_load(const T *ck, bool active, int tid, int cidx, int which,
+                                        T (&vec)[E]) {
+    if (!active) return;
+#pragma unroll
+    for (int z = 0; z < E; ++z) vec[z] = ck[((int64_t)(cidx * 2 + which) * E + z) * (E * E) + tid];
+}
+
+// LDS tables of the atoms of the current box used by the reverse sweep
+template <typename T, int AT, int GA>
+struct AdjShared {
+    Slot slots[AT];
+    T pfac[AT][NP];
+    T dA[GA][NP], gA[GA][3 * NP], dB[GA][NP], gB[GA][3 * NP];
+    double dRacc[GA][3];
+};
+
+// per-region scalars of the reverse sweep
+struct AdjNode {
+    int64_t col, plane;
+    int gz0, n2, cz0, C;
+    bool is_ctr;
+    double gr, gu;
+};
+
+// One reverse step: on entry cur = v_k, nxt = v_{k+1}, ta = vt_{k+1},
+// tb = vt_{k+2}; on exit nxt = v_{k-1} and tb = vt_k (k >= 1).  G += alpha vt_{k+1} v_k,
+// and (GRAD) dR_J += alpha h^3/tau sum_lm c [(vt.dchi)(chi.v) + (vt.chi)(dchi.v)].
+template <typename T, int E, int R, int ZS, int NW, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
+          int AT, int GA>
+__device__ __forceinline__ void adjoint_rstep(const AdjointArgs<T> &aa, const StepCtx<T, E, R> &c,
+                                              const AdjNode &nd, const T (&d)[DREG ? E : 1],
+                                              T *lds, AdjShared<T, AT, GA> &sh, const T *ck,
+                                              int k, T (&cur)[E], T (&nxt)[E], T (&ta)[E],
+                                              T (&tb)[E], T (&G)[E], double tau) {
+    const RegionArgs<T> &a = aa.g;
+    const int tid = threadIdx.x;
+    const bool anchor = k >= 1 && (k - 1) % nd.C == 0;
+    if (anchor) {
+        ck_load<T, E>(ck, c.active, tid, (k - 1) / nd.C, 1, cur);
+        ck_load<T, E>(ck, c.active, tid, (k - 1) / nd.C, 0, nxt);
+    }
+    const T alpha = k == 0 ? (T)1 : (T)2;
+#pragma unroll
+    for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * cur[z];
+    if (k >= 1) {
+        region_step<T, E, R, ZS, NW, MASKZ, DREG, GRAD>(a, c, d, nd.col, nd.plane, nd.gz0, nd.n2,
+                                                        ta, tb, lds, sh.slots, sh.pfac, false, tau,
+                                                        sh.dA, sh.gA);
+        if (nd.is_ctr) {
+            const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
+#pragma unroll
+            for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
+        }
+        if (anchor) {
+            if constexpr (GRAD)
+                dots_only<T, E, R, ZS, NW, GRAD>(a, c, cur, lds, sh.slots, sh.pfac, sh.dB, sh.gB,
+                                                 tau);
+        } else {
+            region_step<T, E, R, ZS, NW, MASKZ, DREG, GRAD>(a, c, d, nd.col, nd.plane, nd.gz0,
+                                                            nd.n2, cur, nxt, lds, sh.slots,
+                                                            sh.pfac, false, tau, sh.dB, sh.gB);
+        }
+    } else {
+        if constexpr (GRAD) {
+            dots_only<T, E, R, ZS, NW, GRAD>(a, c, ta, lds, sh.slots, sh.pfac, sh.dA, sh.gA, tau);
+            dots_only<T, E, R, ZS, NW, GRAD>(a, c, cur, lds, sh.slots, sh.pfac, sh.dB, sh.gB, tau);
+        }
+    }
+    if constexpr (GRAD) {
+        const double f = (double)alpha * a.h3 / tau;
+        for (int j = tid; j < c.nat; j += BLOCK) {
+            const double *cj = a.cJ + (int64_t)sh.slots[j].atom * NP;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < NP; ++l)
+                    s += cj[l] * ((double)sh.gA[j][3 * l + x] * (double)sh.dB[j][l] +
+                                  (double)sh.dA[j][l] * (double)sh.gB[j][3 * l + x]);
+                sh.dRacc[j][x] += f * s;
+            }
+        }
+    }
+}
+
+// Reverse step with the column projector path: the vt and v recurrences keep
+// their own projection buffers (nlA, nlB); the dR term reads the raw
+// projections each step left behind.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD>
+__device__ __forceinline__ void adjoint_rstep_col(const AdjointArgs<T> &aa,
+                                                  const StepCtx<T, E, R> &c, const AdjNode &nd,
+                                                  const T (&d)[DREG ? E : 1], T *lds,
+                                                  ColNL<T> &nlA, ColNL<T> &nlB, const Slot *slots,
+                                                  double (*dRacc)[3], const T *ck, int k,
+                                                  T (&cur)[E], T (&nxt)[E], T (&ta)[E],
+                                                  T (&tb)[E], T (&G)[E], double tau) {
+    const RegionArgs<T> &a = aa.g;
+    const int tid = threadIdx.x;
+    const bool anchor = k >= 1 && (k - 1) % nd.C == 0;
+    if (anchor) {
+        ck_load<T, E>(ck, c.active, tid, (k - 1) / nd.C, 1, cur);
+        ck_load<T, E>(ck, c.active, tid, (k - 1) / nd.C, 0, nxt);
+    }
+    const T alpha = k == 0 ? (T)1 : (T)2;
+#pragma unroll
+    for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * cur[z];
+    if (k >= 1) {
+        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(a, c, d, nd.col, nd.plane, nd.gz0,
+                                                               nd.n2, ta, tb, lds, nlA, false);
+        if (nd.is_ctr) {
+            const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
+#pragma unroll
+            for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
+        }
+        if (anchor) {
+            if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, cur, nlB);
+        } else {
+            region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(a, c, d, nd.col, nd.plane,
+                                                                   nd.gz0, nd.n2, cur, nxt, lds,
+                                                                   nlB, false);
+        }
+    } else {
+        if constexpr (GRAD) {
+            col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, ta, nlA);
+            col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, cur, nlB);
+        }
+    }
+    if constexpr (GRAD) {
+        const double f = (double)alpha * a.h3 / tau;
+        const T *dA = nlA.pacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * NP;
+        const T *gA = nlA.gacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * 3 * NP;
+        const T *dB = nlB.pacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * NP;
+        const T *gB = nlB.gacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * 3 * NP;
+        for (int j = tid; j < c.nat; j += BLOCK) {
+            const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < NP; ++l)
+                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)dB[j * NP + l] +
+                                  (double)dA[j * NP + l] * (double)gB[(j * NP + l) * 3 + x]);
+                dRacc[j][x] += f * s;
+            }
+        }
+    }
+}
+
+// Reverse step when the forward pass stored every v_k (checkpoint stride 1):
+// cur <- v_k from HBM, G += alpha vt_{k+1} v_k, tb <- vt_k; only the adjoint
+// recurrence applies Hs, so four pencils are resident instead of five.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD>
+__device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
+                                                 const StepCtx<T, E, R> &c, const AdjNode &nd,
+                                                 const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
+                                                 ColNL<T> &nlB, const Slot *slots,
+                                                 double (*dRacc)[3], const T *ck, int k,
+                                                 T (&cur)[E], T (&ta)[E], T (&tb)[E], T (&G)[E],
+                                                 double tau) {
+    const RegionArgs<T> &a = aa.g;
+    const int tid = threadIdx.x;
+    if (c.active) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) cur[z] = ck[((int64_t)k * E + z) * (E * E) + tid];
+    }
+    const T alpha = k == 0 ? (T)1 : (T)2;
+#pragma unroll
+    for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * cur[z];
+    if (k >= 1) {
+        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
+            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false);
+        if (nd.is_ctr) {
+            const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
+#pragma unroll
+            for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
+        }
+    } else {
+        if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, ta, nlA);
+    }
+    if constexpr (GRAD) {
+        col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, cur, nlB);
+        const double f = (double)alpha * a.h3 / tau;
+        const T *dA = nlA.pacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * NP;
+        const T *gA = nlA.gacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * 3 * NP;
+        const T *dB = nlB.pacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * NP;
+        const T *gB = nlB.gacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * 3 * NP;
+        for (int j = tid; j < c.nat; j += BLOCK) {
+            const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < NP; ++l)
+                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)dB[j * NP + l] +
+                                  (double)dA[j * NP + l] * (double)gB[(j * NP + l) * 3 + x]);
+                dRacc[j][x] += f * s;
+            }
+        }
+    }
+}
+
+template <typename T, int E, int R, bool MASKZ, bool GRAD, bool STOREALL>
 __global__ void __launch_bounds__(((E * E + 63) / 64) * 64)
 cheb_adjoint_kernel(const AdjointArgs<T> aa) {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
     constexpr int ZS = pencil_stride<T, E>();
     constexpr int NW = BLOCK / 64;
+    constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
+    // column path: two projection states (vt and v), each [2][AT][NP] (+ [2][AT][3NP])
+    constexpr int CEXTRA = (GRAD ? 16 * NP : 4 * NP) * (int)sizeof(T) + (GRAD ? 24 : 0);
+    constexpr bool COLNL = max_atoms_in_region<T, E, CEXTRA, COLBYTES>() >= 32;
     constexpr int EXTRA = GRAD ? (8 * NP * (int)sizeof(T) + 24) : 0;
-    constexpr int MAXAT = max_atoms_in_region<T, E, EXTRA>();
+    constexpr int MAXAT = COLNL ? max_atoms_in_region<T, E, CEXTRA, COLBYTES>()
+                                : max_atoms_in_region<T, E, EXTRA>();
     constexpr int AT = MAXAT > 0 ? MAXAT : 1;
-    constexpr int GA = GRAD ? AT : 1;
+    constexpr int GA = (GRAD && !COLNL) ? AT : 1;
+    constexpr int CA = COLNL ? AT : 1;
+    constexpr int CG = (COLNL && GRAD) ? AT : 1;
     constexpr bool DREG = sizeof(T) == 4 ? E <= 21 : E <= 13;
     constexpr int EE = E * E;
     const RegionArgs<T> &a = aa.g;
 
     __shared__ __align__(16) T lds[region_lds_elems<T, E>()];
-    __shared__ Slot slots[AT];
-    __shared__ T pfac[AT][NP];
-    __shared__ T dA[GA][NP], gA[GA][3 * NP], dB[GA][NP], gB[GA][3 * NP];
-    __shared__ double dRacc[GA][3];
+    __shared__ AdjShared<T, AT, GA> sh;
+    __shared__ T cpA[2][CA][NP], cpB[2][CA][NP];
+    __shared__ T cgA[2][CG][3 * NP], cgB[2][CG][3 * NP];
+    __shared__ double cdR[COLNL && GRAD ? AT : 1][3];
+    __shared__ ColEntry colbuf[COLNL ? BLOCK * MAXC : 1];
+    __shared__ T ncoef[4 * R];
     __shared__ int s_item, s_nat;
+    Slot *slots = sh.slots;
+    T(*pfac)[NP] = sh.pfac;
 
     const int tid = threadIdx.x;
     const double tau = a.scal->tau;
@@ -70,6 +291,11 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
         c.cz[p] = (T)(-a.w[p] * a.ih2[2] / tau);
     }
     T *ck = aa.ckpt + (int64_t)blockIdx.x * aa.ckpt_stride;
+    if (tid < 4 * R) {
+        const int p = (tid >> 2) + 1;
+        ncoef[tid] = (T)(-a.w[p] * a.ih2[(tid & 3) < 2 ? 0 : 1] / tau);
+    }
+    c.ncoef = ncoef;
 
     for (;;) {
         if (tid == 0) {
@@ -117,124 +343,168 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             c.nb[4 * (p - 1) + 3] = (c.active && py - p >= 0) ? tid - p * c.dx : npen;
         }
         c.mine = lds + tid * ZS;
+        c.px = px;
+        c.py = py;
+        c.npen = npen;
         __syncthreads();
         c.nat = min(s_nat, MAXAT);
         if (tid == 0 && s_nat > MAXAT) atomicOr(a.status, 1);
         if constexpr (GRAD) {
-            for (int j = tid; j < c.nat; j += BLOCK) dRacc[j][0] = dRacc[j][1] = dRacc[j][2] = 0.0;
+            for (int j = tid; j < c.nat; j += BLOCK)
+                sh.dRacc[j][0] = sh.dRacc[j][1] = sh.dRacc[j][2] = 0.0;
         }
-        // cotangent coefficients of this node
-        const double gr = aa.g_rho ? aa.g_rho[it.out] : 0.0;
-        const double gu = aa.g_u ? aa.g_u[it.out] : 0.0;
-        auto coef = [&](int k) { return (T)(2.0 * (gr * aa.coef_c[k] + gu * aa.coef_d[k])); };
+        AdjNode nd;
+        nd.col = col;
+        nd.plane = plane;
+        nd.gz0 = gz0;
+        nd.n2 = n2;
+        nd.cz0 = cz0;
+        nd.C = C;
+        nd.is_ctr = is_ctr;
+        nd.gr = aa.g_rho ? aa.g_rho[it.out] : 0.0;
+        nd.gu = aa.g_u ? aa.g_u[it.out] : 0.0;
 
-        auto ck_store = [&](int cidx, int which, const T(&vec)[E]) {
-            if (!c.active) return;
+        ColNL<T> nlA{}, nlB{};
+        if constexpr (COLNL) {
+            for (int j = tid; j < c.nat; j += BLOCK) {
+                const double f = 2.0 * a.h3 / tau;
+                const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
 #pragma unroll
-            for (int z = 0; z < E; ++z) ck[((int64_t)(cidx * 2 + which) * E + z) * EE + tid] = vec[z];
-        };
-        auto ck_load = [&](int cidx, int which, T(&vec)[E]) {
-            if (!c.active) return;
-#pragma unroll
-            for (int z = 0; z < E; ++z) vec[z] = ck[((int64_t)(cidx * 2 + which) * E + z) * EE + tid];
-        };
-
-        // ---- forward: v_0 .. v_K, checkpoints (v_cC, v_cC+1) for cC+1 <= K-1 ----
-        T v[E], w[E];
-#pragma unroll
-        for (int z = 0; z < E; ++z) {
-            v[z] = (is_ctr && z == cz0) ? (T)1 : (T)0;
-            w[z] = (T)0;
-        }
-        for (int k = 0; k < K; k += 2) {
-            region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, v, w, lds, slots,
-                                                      pfac, k == 0, tau);
-            if (k % C == 0 && k + 1 <= K - 1) {
-                ck_store(k / C, 0, v);
-                ck_store(k / C, 1, w);
-            }
-            if (k + 1 < K) {
-                region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, w, v, lds,
-                                                          slots, pfac, false, tau);
-                if ((k + 1) % C == 0 && k + 2 <= K - 1) {
-                    ck_store((k + 1) / C, 0, w);
-                    ck_store((k + 1) / C, 1, v);
+                for (int l = 0; l < NP; ++l) {
+                    pfac[j][l] = (T)(f * cj[l]);
+                    cpA[0][j][l] = cpA[1][j][l] = cpB[0][j][l] = cpB[1][j][l] = (T)0;
+                }
+                if constexpr (GRAD) {
+                    for (int q = 0; q < 3 * NP; ++q)
+                        cgA[0][j][q] = cgA[1][j][q] = cgB[0][j][q] = cgB[1][j][q] = (T)0;
+                    cdR[j][0] = cdR[j][1] = cdR[j][2] = 0.0;
                 }
             }
-        }
-        // (v_{K-1}, v_K) into (v, w)
-        if ((K - 1) % 2) {
-#pragma unroll
-            for (int z = 0; z < E; ++z) {
-                const T t = v[z];
-                v[z] = w[z];
-                w[z] = t;
+            int ncol = build_columns<T>(a, slots, c.nat, c.active, px, py, c.dz, colbuf + tid * MAXC);
+            if (ncol > MAXC) {
+                atomicOr(a.status, 2);
+                ncol = MAXC;
             }
+            nlA.cols = nlB.cols = colbuf + tid * MAXC;
+            nlA.ncol = nlB.ncol = ncol;
+            nlA.scale = nlB.scale = &pfac[0][0];
+            nlA.maxat = nlB.maxat = CA;
+            nlA.pacc = &cpA[0][0][0];
+            nlB.pacc = &cpB[0][0][0];
+            nlA.gacc = GRAD ? &cgA[0][0][0] : nullptr;
+            nlB.gacc = GRAD ? &cgB[0][0][0] : nullptr;
+            __syncthreads();
         }
 
-        // ---- reverse sweep ----
-        T t1[E], t2[E], G[E];
-        {
-            const T aK = coef(K);
+        T v[E], G[E];
+        if constexpr (COLNL && STOREALL) {
+            // ---- forward storing v_0 .. v_{K-1}; reverse reads them back ----
+            T w[E];
+#pragma unroll
+            for (int z = 0; z < E; ++z) {
+                v[z] = (is_ctr && z == cz0) ? (T)1 : (T)0;
+                w[z] = (T)0;
+            }
+            // slot layout [k][z][pencil]: a wave's stores coalesce
+            // (v_K itself is never needed by the reverse sweep)
+            ck_store<T, E>(ck, c.active, tid, 0, 0, v);
+            for (int k = 0; k + 1 <= K - 1; k += 2) {
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(
+                    a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0);
+                ck_store<T, E>(ck, c.active, tid, 0, k + 1, w);
+                if (k + 2 <= K - 1) {
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(
+                        a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false);
+                    ck_store<T, E>(ck, c.active, tid, 0, k + 2, v);
+                }
+            }
+            T t1[E], t2[E];
+            const T aK = (T)(2.0 * (nd.gr * aa.coef_c[K] + nd.gu * aa.coef_d[K]));
 #pragma unroll
             for (int z = 0; z < E; ++z) {
                 t1[z] = (is_ctr && z == cz0) ? aK : (T)0;
                 t2[z] = (T)0;
                 G[z] = (T)0;
             }
-        }
-        // One reverse step: on entry cur = v_k, nxt = v_{k+1}, ta = vt_{k+1},
-        // tb = vt_{k+2}; on exit nxt = v_{k-1} and tb = vt_k (k >= 1).
-        auto rstep = [&](int k, T(&cur)[E], T(&nxt)[E], T(&ta)[E], T(&tb)[E]) {
-            const bool anchor = k >= 1 && (k - 1) % C == 0;
-            if (anchor) {
-                ck_load((k - 1) / C, 1, cur);
-                ck_load((k - 1) / C, 0, nxt);
+            for (int k = K - 1; k >= 0; k -= 2) {
+                adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                    aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k, v, t1, t2, G, tau);
+                if (k - 1 >= 0)
+                    adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                        aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k - 1, v, t2, t1, G, tau);
             }
-            const T alpha = k == 0 ? (T)1 : (T)2;
-#pragma unroll
-            for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * cur[z];
-            if (k >= 1) {
-                region_step<T, E, R, ZS, NW, MASKZ, DREG, GRAD>(a, c, d, col, plane, gz0, n2, ta, tb,
-                                                                lds, slots, pfac, false, tau, dA, gA);
-                if (is_ctr) {
-                    const T ak = coef(k);
-#pragma unroll
-                    for (int z = 0; z < E; ++z) tb[z] += (z == cz0) ? ak : (T)0;
-                }
-                if (anchor) {
-                    if constexpr (GRAD)
-                        dots_only<T, E, R, ZS, NW, GRAD>(a, c, cur, lds, slots, pfac, dB, gB, tau);
-                } else {
-                    region_step<T, E, R, ZS, NW, MASKZ, DREG, GRAD>(a, c, d, col, plane, gz0, n2, cur,
-                                                                    nxt, lds, slots, pfac, false,
-                                                                    tau, dB, gB);
-                }
-            } else {
-                if constexpr (GRAD) {
-                    dots_only<T, E, R, ZS, NW, GRAD>(a, c, ta, lds, slots, pfac, dA, gA, tau);
-                    dots_only<T, E, R, ZS, NW, GRAD>(a, c, cur, lds, slots, pfac, dB, gB, tau);
-                }
+        } else {
+            // ---- forward: v_0 .. v_K, checkpoints (v_cC, v_cC+1) for cC+1 <= K-1 ----
+            T w[E];
+    #pragma unroll
+            for (int z = 0; z < E; ++z) {
+                v[z] = (is_ctr && z == cz0) ? (T)1 : (T)0;
+                w[z] = (T)0;
             }
-            if constexpr (GRAD) {
-                const double f = (double)alpha * a.h3 / tau;
-                for (int j = tid; j < c.nat; j += BLOCK) {
-                    const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int l = 0; l < NP; ++l)
-                            s += cj[l] * ((double)gA[j][3 * l + x] * (double)dB[j][l] +
-                                          (double)dA[j][l] * (double)gB[j][3 * l + x]);
-                        dRacc[j][x] += f * s;
+            for (int k = 0; k < K; k += 2) {
+                if constexpr (COLNL)
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(a, c, d, col, plane, gz0, n2,
+                                                                            v, w, lds, nlB, k == 0);
+                else
+                    region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, v, w, lds,
+                                                              slots, pfac, k == 0, tau);
+                if (k % C == 0 && k + 1 <= K - 1) {
+                    ck_store<T, E>(ck, c.active, tid, k / C, 0, v);
+                    ck_store<T, E>(ck, c.active, tid, k / C, 1, w);
+                }
+                if (k + 1 < K) {
+                    if constexpr (COLNL)
+                        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(a, c, d, col, plane, gz0,
+                                                                                n2, w, v, lds, nlB, false);
+                    else
+                        region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, w, v,
+                                                                  lds, slots, pfac, false, tau);
+                    if ((k + 1) % C == 0 && k + 2 <= K - 1) {
+                        ck_store<T, E>(ck, c.active, tid, (k + 1) / C, 0, w);
+                        ck_store<T, E>(ck, c.active, tid, (k + 1) / C, 1, v);
                     }
                 }
             }
-        };
-        for (int k = K - 1; k >= 0; k -= 2) {
-            rstep(k, v, w, t1, t2);
-            if (k - 1 >= 0) rstep(k - 1, w, v, t2, t1);
+            // (v_{K-1}, v_K) into (v, w)
+            if ((K - 1) % 2) {
+    #pragma unroll
+                for (int z = 0; z < E; ++z) {
+                    const T t = v[z];
+                    v[z] = w[z];
+                    w[z] = t;
+                }
+            }
+
+            // ---- reverse sweep ----
+            T t1[E], t2[E];
+            {
+                const T aK = (T)(2.0 * (nd.gr * aa.coef_c[K] + nd.gu * aa.coef_d[K]));
+    #pragma unroll
+                for (int z = 0; z < E; ++z) {
+                    t1[z] = (is_ctr && z == cz0) ? aK : (T)0;
+                    t2[z] = (T)0;
+                    G[z] = (T)0;
+                }
+            }
+            if constexpr (COLNL) {
+                for (int k = K - 1; k >= 0; k -= 2) {
+                    adjoint_rstep_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                        aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k, v, w, t1, t2, G, tau);
+                    if (k - 1 >= 0)
+                        adjoint_rstep_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                            aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k - 1, w, v, t2, t1, G, tau);
+                }
+            } else {
+                for (int k = K - 1; k >= 0; k -= 2) {
+                    adjoint_rstep<T, E, R, ZS, NW, BLOCK, MASKZ, DREG, GRAD, AT, GA>(
+                        aa, c, nd, d, lds, sh, ck, k, v, w, t1, t2, G, tau);
+                    if (k - 1 >= 0)
+                        adjoint_rstep<T, E, R, ZS, NW, BLOCK, MASKZ, DREG, GRAD, AT, GA>(
+                            aa, c, nd, d, lds, sh, ck, k - 1, w, v, t2, t1, G, tau);
+                }
+            }
+
+
         }
 
         // ---- scatter: dV (FP64 atomics), dR per atom of the box ----
@@ -254,7 +524,8 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             if (aa.dR)
                 for (int j = tid; j < c.nat; j += BLOCK)
                     for (int x = 0; x < 3; ++x)
-                        unsafeAtomicAdd(aa.dR + (int64_t)slots[j].atom * 3 + x, dRacc[j][x]);
+                        unsafeAtomicAdd(aa.dR + (int64_t)slots[j].atom * 3 + x,
+                                        COLNL ? cdR[j][x] : sh.dRacc[j][x]);
         }
         __syncthreads();
     }
@@ -263,34 +534,36 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
 // ------------------------------------------------------------------------- //
 // launch helpers for one FD radius R (instantiated in sq_adjoint_r<R>.hip)
 // ------------------------------------------------------------------------- //
-template <typename T, int E, int R, bool M, bool G>
+// z masking is always on in the adjoint (one select per point and step) so the
+// instantiations cover (gradient) x (store-all or rebuild) only.
+template <typename T, int E, int R, bool G, bool SA>
 static hipError_t adj_launch_one(const void *args, int grid, hipStream_t s) {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
-    hipLaunchKernelGGL((cheb_adjoint_kernel<T, E, R, M, G>), dim3(grid), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((cheb_adjoint_kernel<T, E, R, true, G, SA>), dim3(grid), dim3(BLOCK), 0, s,
                        *static_cast<const AdjointArgs<T> *>(args));
     return hipGetLastError();
 }
 
-template <typename T, int E, int R, bool M, bool G>
+template <typename T, int E, int R, bool G, bool SA>
 static int adj_occ_one() {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cheb_adjoint_kernel<T, E, R, M, G>, BLOCK,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cheb_adjoint_kernel<T, E, R, true, G, SA>,
+                                                     BLOCK, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
 template <typename T, int E, int R>
-static hipError_t adj_by_mg(bool M, bool G, const void *args, int grid, hipStream_t s, int *occ) {
+static hipError_t adj_by_mg(bool SA, bool G, const void *args, int grid, hipStream_t s, int *occ) {
     if (occ) {
-        *occ = M ? (G ? adj_occ_one<T, E, R, true, true>() : adj_occ_one<T, E, R, true, false>())
-                 : (G ? adj_occ_one<T, E, R, false, true>() : adj_occ_one<T, E, R, false, false>());
+        *occ = SA ? (G ? adj_occ_one<T, E, R, true, true>() : adj_occ_one<T, E, R, false, true>())
+                  : (G ? adj_occ_one<T, E, R, true, false>() : adj_occ_one<T, E, R, false, false>());
         return hipSuccess;
     }
-    if (M) return G ? adj_launch_one<T, E, R, true, true>(args, grid, s)
-                    : adj_launch_one<T, E, R, true, false>(args, grid, s);
-    return G ? adj_launch_one<T, E, R, false, true>(args, grid, s)
+    if (SA) return G ? adj_launch_one<T, E, R, true, true>(args, grid, s)
+                     : adj_launch_one<T, E, R, false, true>(args, grid, s);
+    return G ? adj_launch_one<T, E, R, true, false>(args, grid, s)
              : adj_launch_one<T, E, R, false, false>(args, grid, s);
 }
 
@@ -310,10 +583,10 @@ static hipError_t adj_by_e(int E, bool M, bool G, const void *args, int grid, hi
 }
 
 template <int R>
-hipError_t adjoint_dispatch_r(int prec, int E, bool M, bool G, const void *args, int grid,
+hipError_t adjoint_dispatch_r(int prec, int E, bool SA, bool G, const void *args, int grid,
                               hipStream_t s, int *occ) {
-    if (prec == SQ_FP64) return adj_by_e<double, R>(E, M, G, args, grid, s, occ);
-    return adj_by_e<float, R>(E, M, G, args, grid, s, occ);
+    if (prec == SQ_FP64) return adj_by_e<double, R>(E, SA, G, args, grid, s, occ);
+    return adj_by_e<float, R>(E, SA, G, args, grid, s, occ);
 }
 
 }  // namespace sqk

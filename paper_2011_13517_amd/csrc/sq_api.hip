@@ -98,6 +98,8 @@ struct sq_ctx {
     float *d_chi32 = nullptr, *d_dchi32 = nullptr;
     double *d_chi64 = nullptr, *d_dchi64 = nullptr;
     double *d_cJ = nullptr;
+    double *d_chi_full = nullptr;   // caller's row order, whole-domain operator
+    int32_t *d_colidx = nullptr;
     int64_t *d_sup_off = nullptr, *d_sup_idx = nullptr;
     int64_t n_upts = 0;
     int64_t *d_pt_idx = nullptr, *d_pt_off = nullptr, *d_pt_row = nullptr;
@@ -106,6 +108,7 @@ struct sq_ctx {
     FermiWork fw{};
     // adjoint
     bool adj_ok = false;
+    bool storeall = false;
     int grid_adj = 1;
     int n_ckpt = 1;
     int64_t ckpt_stride = 0;
@@ -313,8 +316,9 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
 
     // ---- projectors ------------------------------------------------------
     std::vector<AtomDev> atoms;
-    std::vector<int32_t> pack;
-    std::vector<double> chi64, dchi64, cJ;
+    std::vector<int32_t> rpack, colidx;     // region tables (see below)
+    std::vector<double> rchi, rdchi;
+    std::vector<double> chi64, cJ;
     std::vector<int64_t> sup_off, sup_idx;
     if (proj && proj->n_atoms > 0) {
         if (proj->n_proj < 1 || proj->n_proj > NP)
@@ -329,9 +333,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         if (proj->sup_off[0] != 0 || nnz < 0 || nnz > INT32_MAX)
             return bail(fail(SQ_ERR_ARG, "bad sup_off"));
         atoms.resize(c.n_atoms);
-        pack.resize(nnz);
         chi64.assign(nnz * NP, 0.0);
-        dchi64.assign(nnz * NP * 3, 0.0);
         cJ.assign((size_t)c.n_atoms * NP, 0.0);
         sup_off.assign(proj->sup_off, proj->sup_off + c.n_atoms + 1);
         sup_idx.assign(proj->sup_idx, proj->sup_idx + nnz);
@@ -342,8 +344,9 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
             if (s1 < s0) return bail(fail(SQ_ERR_ARG, "sup_off not monotone"));
             for (int l = 0; l < np; ++l) cJ[(size_t)J * NP + l] = proj->c[(int64_t)J * np + l];
             AtomDev &at = atoms[J];
-            at.start = (int32_t)s0;
-            at.count = (int32_t)(s1 - s0);
+            at.start = (int32_t)rpack.size();
+            at.count = 0;
+            at.col_start = (int32_t)(colidx.size() / 2);
             if (s1 == s0) {
                 for (int a = 0; a < 3; ++a) { at.lo[a] = 0; at.dim[a] = 0; }
                 continue;
@@ -363,6 +366,18 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
                     return bail(fail(SQ_ERR_ARG, "projector support too wide (%d nodes)", at.dim[a]));
                 bbmax[a] = std::max(bbmax[a], at.dim[a]);
             }
+            // whole-domain tables keep the caller's row order
+            for (int64_t s = s0; s < s1; ++s)
+                for (int l = 0; l < np; ++l) chi64[s * NP + l] = proj->chi[s * np + l];
+            // region tables: the support on its box, column-major (x, y) with z
+            // contiguous; a column's rows span its z range (gaps padded with
+            // zero rows) so a pencil's piece of the support is one run of rows.
+            const int bd[3] = {at.dim[0], at.dim[1], at.dim[2]};
+            const int64_t bvol = (int64_t)bd[0] * bd[1] * bd[2];
+            if (bvol > (1LL << 26)) return bail(fail(SQ_ERR_ARG, "projector support box too large"));
+            std::vector<int64_t> where(bvol, -1);   // box cell -> first caller row there
+            std::vector<int> zmin(bd[0] * bd[1], INT32_MAX), zmax(bd[0] * bd[1], -1);
+            std::vector<int64_t> cell(s1 - s0);
             for (int64_t s = s0; s < s1; ++s) {
                 int o[3];
                 for (int a = 0; a < 3; ++a) {
@@ -370,14 +385,46 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
                     if (c.periodic) x = ((x % c.N[a]) + c.N[a]) % c.N[a];
                     o[a] = x;
                 }
-                pack[s] = o[0] | (o[1] << 10) | (o[2] << 20);
-                for (int l = 0; l < np; ++l) {
-                    chi64[s * NP + l] = proj->chi[s * np + l];
-                    if (proj->dchi)
-                        for (int x = 0; x < 3; ++x)
-                            dchi64[(s * NP + l) * 3 + x] = proj->dchi[(s * np + l) * 3 + x];
+                const int col = o[1] * bd[0] + o[0];
+                zmin[col] = std::min(zmin[col], o[2]);
+                zmax[col] = std::max(zmax[col], o[2]);
+                const int64_t ci = (int64_t)col * bd[2] + o[2];
+                cell[s - s0] = ci;
+                if (where[ci] < 0) where[ci] = s;
+            }
+            at.start = (int32_t)(rpack.size());
+            at.col_start = (int32_t)(colidx.size() / 2);
+            for (int col = 0; col < bd[0] * bd[1]; ++col) {
+                if (zmax[col] < 0) {
+                    colidx.push_back(0);
+                    colidx.push_back(0);
+                    continue;
+                }
+                const int n = zmax[col] - zmin[col] + 1;
+                colidx.push_back((int32_t)rpack.size());
+                colidx.push_back(zmin[col] | (n << 16));
+                for (int z = zmin[col]; z <= zmax[col]; ++z) {
+                    rpack.push_back((col % bd[0]) | ((col / bd[0]) << 10) | (z << 20));
+                    for (int q = 0; q < NP; ++q) rchi.push_back(0.0);
+                    for (int q = 0; q < 3 * NP; ++q) rdchi.push_back(0.0);
                 }
             }
+            // scatter the caller's rows (rows at the same cell add up, which
+            // leaves both the projections and the rank-4 term unchanged)
+            for (int64_t s = s0; s < s1; ++s) {
+                const int64_t ci = cell[s - s0];
+                const int col = (int)(ci / bd[2]), z = (int)(ci % bd[2]);
+                const int64_t row = colidx[2 * ((int64_t)at.col_start + col)] + (z - zmin[col]);
+                for (int l = 0; l < np; ++l) {
+                    rchi[row * NP + l] += proj->chi[s * np + l];
+                    if (proj->dchi)
+                        for (int x = 0; x < 3; ++x)
+                            rdchi[(row * NP + l) * 3 + x] += proj->dchi[(s * np + l) * 3 + x];
+                }
+            }
+            at.count = (int32_t)(rpack.size() - at.start);
+            if (rpack.size() > (size_t)INT32_MAX / 16)
+                return bail(fail(SQ_ERR_ARG, "projector tables too large"));
         }
         if (c.periodic)
             for (int a = 0; a < 3; ++a)
@@ -414,17 +461,21 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     ALLOC(c.d_mpartial, (size_t)c.n_mpart * K1);
     if (c.n_atoms) {
         UPLOAD(c.d_atoms, atoms.data(), atoms.size());
-        UPLOAD(c.d_pack, pack.data(), pack.size());
-        UPLOAD(c.d_chi64, chi64.data(), chi64.size());
+        UPLOAD(c.d_pack, rpack.data(), rpack.size());
+        UPLOAD(c.d_colidx, colidx.data(), colidx.size());
+        UPLOAD(c.d_chi_full, chi64.data(), chi64.size());
         UPLOAD(c.d_cJ, cJ.data(), cJ.size());
         UPLOAD(c.d_sup_off, sup_off.data(), sup_off.size());
         UPLOAD(c.d_sup_idx, sup_idx.data(), sup_idx.size());
-        if (c.have_dchi) UPLOAD(c.d_dchi64, dchi64.data(), dchi64.size());
+        if (c.prec == SQ_FP64 || c.aprec == SQ_FP64) {
+            UPLOAD(c.d_chi64, rchi.data(), rchi.size());
+            if (c.have_dchi) UPLOAD(c.d_dchi64, rdchi.data(), rdchi.size());
+        }
         if (c.prec == SQ_FP32_ACC64 || c.aprec == SQ_FP32_ACC64) {
-            std::vector<float> f(chi64.begin(), chi64.end());
+            std::vector<float> f(rchi.begin(), rchi.end());
             UPLOAD(c.d_chi32, f.data(), f.size());
             if (c.have_dchi) {
-                std::vector<float> g(dchi64.begin(), dchi64.end());
+                std::vector<float> g(rdchi.begin(), rdchi.end());
                 UPLOAD(c.d_dchi32, g.data(), g.size());
             }
         }
@@ -480,15 +531,30 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         return bail(fail(SQ_ERR_HIP, "hipMemset failed"));
     const int occ = forward_blocks_per_cu(c.prec, c.E, c.r, c.maskz);
     c.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, c.n_items));
-    // adjoint: one checkpoint slot of ceil((K-1)/C) box pairs per resident workgroup
+    // adjoint: one checkpoint slot per resident workgroup
     c.adj_ok = c.E <= adjoint_max_edge(c.aprec);
     if (c.adj_ok) {
         const bool grad = c.n_atoms > 0 && c.have_dchi;
-        const int aocc = adjoint_blocks_per_cu(c.aprec, c.E, c.r, c.maskz, grad);
+        const int64_t e3 = (int64_t)c.E * c.E * c.E;
+        const int64_t esz = c.aprec == SQ_FP64 ? 8 : 4;
+        // stride 1 keeps every v_k of the in-flight regions (no rebuild, two
+        // operator applications per step); chosen by default when that pool
+        // stays below 8 GiB
+        const int aocc_sa = adjoint_blocks_per_cu(c.aprec, c.E, c.r, true, grad);
+        const int64_t grid_sa = std::max<int64_t>(1, std::min<int64_t>((int64_t)aocc_sa * ncu, c.n_items));
+        const int64_t pool_sa = grid_sa * c.K * e3 * esz;
+        c.storeall = params->ckpt_every == 1 ||
+                     (params->ckpt_every == 0 && pool_sa <= (int64_t)8 << 30);
+        // a store-all kernel without the column projector path (never the case
+        // for the supported edges, but kept well defined) rebuilds with stride 10
+        if (c.storeall) c.p.ckpt_every = 10;
+        const int aocc = adjoint_blocks_per_cu(c.aprec, c.E, c.r, c.storeall, grad);
         c.grid_adj = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)aocc * ncu, c.n_items));
         c.n_ckpt = c.K >= 2 ? (c.K - 2) / c.p.ckpt_every + 1 : 1;
-        const int64_t e3 = (int64_t)c.E * c.E * c.E;
+        // a kernel without the column projector path falls back to the rebuild
+        // layout, so a store-all pool also covers that one
         c.ckpt_stride = (int64_t)c.n_ckpt * 2 * e3;
+        if (c.storeall) c.ckpt_stride = std::max<int64_t>(c.ckpt_stride, (int64_t)c.K * e3);
         const size_t n = (size_t)c.grid_adj * c.ckpt_stride;
         if (c.aprec == SQ_FP64) {
             double *q = nullptr;
@@ -553,7 +619,7 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
         op.n_atoms = c.n_atoms;
         op.sup_off = c.d_sup_off;
         op.sup_idx = c.d_sup_idx;
-        op.chi = c.d_chi64;
+        op.chi = c.d_chi_full;
         op.cJ = c.d_cJ;
         op.n_upts = c.n_upts;
         op.pt_idx = c.d_pt_idx;
@@ -584,6 +650,7 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
         a.n_atoms = c.n_atoms;
         a.atoms = c.d_atoms;
         a.sup_pack = c.d_pack;
+        a.colidx = c.d_colidx;
         a.chi = c.d_chi64;
         a.dchi = c.d_dchi64;
         a.cJ = c.d_cJ;
@@ -605,6 +672,7 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
         a.n_atoms = c.n_atoms;
         a.atoms = c.d_atoms;
         a.sup_pack = c.d_pack;
+        a.colidx = c.d_colidx;
         a.chi = c.d_chi32;
         a.dchi = c.d_dchi32;
         a.cJ = c.d_cJ;
@@ -665,6 +733,7 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
         g.n_atoms = c.n_atoms;
         g.atoms = c.d_atoms;
         g.sup_pack = c.d_pack;
+        g.colidx = c.d_colidx;
         g.cJ = c.d_cJ;
         g.status = c.d_status;
     };
@@ -684,7 +753,7 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
         a.ckpt_every = c.p.ckpt_every;
         a.n_ckpt = c.n_ckpt;
         a.ckpt_stride = c.ckpt_stride;
-        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.maskz, grad, &a, c.grid_adj, st));
+        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.storeall, grad, &a, c.grid_adj, st));
     } else {
         AdjointArgs<float> a{};
         fill(a.g);
@@ -701,7 +770,7 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
         a.ckpt_every = c.p.ckpt_every;
         a.n_ckpt = c.n_ckpt;
         a.ckpt_stride = c.ckpt_stride;
-        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.maskz, grad, &a, c.grid_adj, st));
+        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.storeall, grad, &a, c.grid_adj, st));
     }
     c.last_stream = st;
     return SQ_OK;

@@ -17,9 +17,15 @@
 //   2 Hs v_k = D v_k + sum_p a_{p,x}(v[x+p] + v[x-p]) + ... (LDS for x and y,
 //              registers for z) + 2 (h^3/tau) sum_J sum_lm c_Jl chi (chi . v_k)
 // and v_{k+1} = 2 Hs v_k - v_{k-1} stays in its registers.  The nonlocal
-// projector block runs wave-per-atom on the LDS copy: the wave reduces the
-// four dot products chi_Jlm . v_k over the atom's support inside the box,
-// then adds the rank-4 update back with LDS atomics.
+// projector block works per pencil: each thread projects its own pencil (read
+// back from LDS) onto the pieces of atom supports that cross it, the four dot
+// products chi_Jlm . v_k of every atom are reduced over the box with LDS
+// atomics, and after the step's second barrier each thread adds the rank-4
+// term to its own pencil (no atomics, no extra pass, no extra barrier).  The
+// projector tables are stored column-major per atom with a column index, so a
+// pencil's piece of a support is one contiguous run of rows.  When the box
+// and the column tables do not fit the LDS (FP64 at edge 27), a wave-per-atom
+// two-pass variant is used instead.
 #include "sq_region.h"
 
 namespace sqk {
@@ -30,12 +36,18 @@ cheb_forward_kernel(const RegionArgs<T> a) {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
     constexpr int ZS = pencil_stride<T, E>();
     constexpr int NW = BLOCK / 64;
-    constexpr int MAXAT = max_atoms_in_region<T, E>();
+    constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
+    constexpr bool COLNL = max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>() >= 32;
+    constexpr int MAXAT = COLNL ? max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>()
+                                : max_atoms_in_region<T, E>();
+    constexpr int AT = MAXAT > 0 ? MAXAT : 1;
     constexpr bool DREG = sizeof(T) == 4 || E <= 17;   // keep D in VGPRs when it fits
 
     __shared__ __align__(16) T lds[region_lds_elems<T, E>()];
-    __shared__ Slot slots[MAXAT > 0 ? MAXAT : 1];
-    __shared__ T pfac[MAXAT > 0 ? MAXAT : 1][NP];
+    __shared__ Slot slots[AT];
+    __shared__ T pfac[AT][NP];                       // column path: 2 h^3 c / tau
+    __shared__ T pacc[COLNL ? 2 : 1][COLNL ? AT : 1][NP];
+    __shared__ ColEntry colbuf[COLNL ? BLOCK * MAXC : 1];
     __shared__ int s_item, s_nat;
 
     const int tid = threadIdx.x;
@@ -115,6 +127,40 @@ cheb_forward_kernel(const RegionArgs<T> a) {
         c.nat = min(s_nat, MAXAT);
         if (tid == 0 && s_nat > MAXAT) atomicOr(a.status, 1);
 
+        ColNL<T> nl{};
+        if constexpr (COLNL) {
+            for (int j = tid; j < c.nat; j += BLOCK) {
+                const double f = 2.0 * a.h3 / tau;
+                const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) {
+                    pfac[j][l] = (T)(f * cj[l]);
+                    pacc[0][j][l] = (T)0;
+                    pacc[1][j][l] = (T)0;
+                }
+            }
+            int ncol = build_columns<T>(a, slots, c.nat, c.active, px, py, c.dz, colbuf + tid * MAXC);
+            if (ncol > MAXC) {
+                atomicOr(a.status, 2);
+                ncol = MAXC;
+            }
+            nl.cols = colbuf + tid * MAXC;
+            nl.ncol = ncol;
+            nl.pacc = &pacc[0][0][0];
+            nl.scale = &pfac[0][0];
+            nl.maxat = AT;
+            __syncthreads();
+            for (int k = 0; k < K; k += 2) {
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false>(a, c, d, col, plane, gz0, n2,
+                                                                        v, w, lds, nl, k == 0);
+                if (is_ctr) mu[k + 1] = pick(w, cz0);
+                if (k + 1 < K) {
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false>(a, c, d, col, plane, gz0,
+                                                                            n2, w, v, lds, nl, false);
+                    if (is_ctr) mu[k + 2] = pick(v, cz0);
+                }
+            }
+        } else {
         // ping-pong: the newest vector alternates between v and w
         for (int k = 0; k < K; k += 2) {
             region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, v, w, lds, slots, pfac,
@@ -125,6 +171,7 @@ cheb_forward_kernel(const RegionArgs<T> a) {
                                                           false, tau);
                 if (is_ctr) mu[k + 2] = pick(v, cz0);
             }
+        }
         }
         __syncthreads();
     }

@@ -29,8 +29,10 @@ struct Item {
 struct AtomDev {
     int32_t lo[3];
     int32_t dim[3];
-    int32_t start;
+    int32_t start;      // first row of the region tables (column-major support)
     int32_t count;
+    int32_t col_start;  // first column of the atom in the column index
+    int32_t pad_;
 };
 
 // Device-resident scalars of a context (all FP64 unless integer).
@@ -68,6 +70,7 @@ struct RegionArgs {
     int32_t n_atoms;
     const AtomDev *atoms;
     const int32_t *sup_pack;   // packed (x | y << 10 | z << 20) offsets in the atom box
+    const int32_t *colidx;     // per atom column (x, y) of its box: {first row, zoff | n << 16}
     const T *chi;              // [nnz][NP]
     const T *dchi;             // [nnz][NP][3]
     const double *cJ;          // [n_atoms][NP]
@@ -84,7 +87,7 @@ struct AdjointArgs {
     const double *g_u;         // [n_nodes] or null
     double *dV;                // V grid, accumulated, or null
     double *dR;                // [n_atoms][3], accumulated, or null
-    T *ckpt;                   // checkpoint pool: [grid][n_ckpt][2][E^3]
+    T *ckpt;                   // per workgroup: [n_ckpt][2][E^3] pairs, or [K][E^3] (store-all)
     int32_t ckpt_every;
     int32_t n_ckpt;
     int64_t ckpt_stride;       // elements per workgroup slot
@@ -95,9 +98,11 @@ struct AdjointArgs {
 hipError_t launch_forward(int prec, int E, int R, bool maskz, const void *args, int grid,
                           hipStream_t s);
 int forward_blocks_per_cu(int prec, int E, int R, bool maskz);
-hipError_t launch_adjoint(int prec, int E, int R, bool maskz, bool grad, const void *args,
+// storeall: the forward pass keeps every v_k (checkpoint stride 1) instead
+// of checkpoints every ckpt_every steps plus the reverse rebuild.
+hipError_t launch_adjoint(int prec, int E, int R, bool storeall, bool grad, const void *args,
                           int grid, hipStream_t s);
-int adjoint_blocks_per_cu(int prec, int E, int R, bool maskz, bool grad);
+int adjoint_blocks_per_cu(int prec, int E, int R, bool storeall, bool grad);
 int adjoint_max_edge(int prec);
 
 // Region-edge buckets with a compiled kernel (the largest edge of every box

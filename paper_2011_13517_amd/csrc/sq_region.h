@@ -11,16 +11,27 @@ struct Slot {              // an atom touching the current box
     int32_t start, count;  // rows in the support tables
     int32_t ox, oy, oz;    // atom box origin relative to the region box
     int32_t atom;
+    int32_t bx, by;        // atom box extent in x and y
+    int32_t col;           // first entry of the atom's column index
 };
 
-// atoms per region that fit the LDS left over by the box (EXTRA bytes of
-// per-atom state beyond the slot and its four scaled projections)
-template <typename T, int E, int EXTRA = 0>
+// Column path of the projector block: every thread handles the pieces of
+// atom supports that cross its own z-pencil.  An entry names the atom slot,
+// the first support row of the piece and its z range in the box.
+constexpr int MAXC = 4;    // supports crossing one pencil of a box
+struct ColEntry {
+    int32_t slot, row0, zlo, n;
+};
+
+// atoms per region that fit the LDS left over by the box and FIXED bytes of
+// other tables (EXTRA bytes of per-atom state beyond the slot and its four
+// scaled projections)
+template <typename T, int E, int EXTRA = 0, int FIXED = 0>
 constexpr int max_atoms_in_region() {
-    constexpr int used = region_lds_elems<T, E>() * (int)sizeof(T) + 512;
+    constexpr int used = region_lds_elems<T, E>() * (int)sizeof(T) + 512 + FIXED;
     constexpr int per = (int)sizeof(Slot) + NP * (int)sizeof(T) + EXTRA;
     constexpr int n = (LDS_BYTES - used) / per;
-    return n > 128 ? 128 : n;
+    return n > 128 ? 128 : (n < 0 ? 0 : n);
 }
 
 template <typename T, int E, int ZS>
@@ -136,6 +147,9 @@ __device__ void gather_atoms(const RegionArgs<T> &a, const Item &it, Slot *slots
                 slots[slot].oy = off[1];
                 slots[slot].oz = off[2];
                 slots[slot].atom = j;
+                slots[slot].bx = at.dim[0];
+                slots[slot].by = at.dim[1];
+                slots[slot].col = at.col_start;
             }
         }
     }
@@ -150,6 +164,8 @@ struct StepCtx {
     int nat;
     bool active;
     T *mine;
+    int px, py, npen;      // pencil of this thread, pencils in the box
+    const T *ncoef;        // LDS [4R]: x+, x-, y+, y- weights per distance (low-register path)
 };
 
 // Raw projections of the LDS vector onto the projectors of every atom of the
@@ -294,6 +310,238 @@ __device__ __forceinline__ void region_step(const RegionArgs<T> &a, const StepCt
 #pragma unroll
         for (int z = 0; z < E; ++z) prev[z] = (z < c.dz) ? prev[z] : (T)0;
     }
+}
+
+// --------------------------------------------------------------------------
+// Column path of the projector block.
+// --------------------------------------------------------------------------
+template <typename T>
+struct ColNL {
+    const ColEntry *cols;  // this thread's entries (LDS)
+    int ncol;
+    T *pacc;               // [2][maxat][NP] raw projections chi . v, by step parity
+    T *gacc;               // [2][maxat][3 NP] raw d chi / d R . v (gradient), or null
+    const T *scale;        // [maxat][NP] 2 h^3 c_Jl / tau
+    int maxat;
+    int par;               // parity buffer of the current step (zero on entry)
+};
+
+// entries of the atom supports crossing pencil (px, py) of the box
+template <typename T>
+__device__ __forceinline__ int build_columns(const RegionArgs<T> &a, const Slot *slots, int nat,
+                                             bool active, int px, int py, int dz, ColEntry *mine) {
+    int n = 0;
+    if (!active) return 0;
+    for (int j = 0; j < nat; ++j) {
+        const Slot sl = slots[j];
+        const int cx = px - sl.ox, cy = py - sl.oy;
+        if (cx < 0 || cy < 0 || cx >= sl.bx || cy >= sl.by) continue;
+        const int64_t ci = 2 * ((int64_t)sl.col + (int64_t)cy * sl.bx + cx);
+        const int row = a.colidx[ci], zc = a.colidx[ci + 1];
+        const int cnt = zc >> 16;
+        if (cnt == 0) continue;
+        const int z0 = sl.oz + (zc & 0xffff);
+        const int zlo = max(z0, 0), zhi = min(z0 + cnt, dz);
+        if (zlo >= zhi) continue;
+        if (n < MAXC) mine[n] = ColEntry{j, row + (zlo - z0), zlo, zhi - zlo};
+        ++n;
+    }
+    return n;
+}
+
+// raw projections of this thread's pencil (in LDS) onto the crossing supports,
+// reduced over the box with LDS atomics into the current parity buffer
+template <typename T, bool GRAD>
+__device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
+                                         const T *pencil) {
+    for (int c = 0; c < nl.ncol; ++c) {
+        const ColEntry e = nl.cols[c];
+        T s[NP] = {0, 0, 0, 0};
+        T g[GRAD ? 3 * NP : 1];
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int i = 0; i < 3 * NP; ++i) g[i] = 0;
+        }
+        for (int i = 0; i < e.n; ++i) {
+            const T v = pencil[e.zlo + i];
+            const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
+#pragma unroll
+            for (int l = 0; l < NP; ++l) s[l] += ch[l] * v;
+            if constexpr (GRAD) {
+                const T *dc = a.dchi + (int64_t)(e.row0 + i) * 3 * NP;
+#pragma unroll
+                for (int q = 0; q < 3 * NP; ++q) g[q] += dc[q] * v;
+            }
+        }
+        T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) atomicAdd(&pa[l], s[l]);
+        if constexpr (GRAD) {
+            T *ga = nl.gacc + ((int64_t)nl.par * nl.maxat + e.slot) * 3 * NP;
+#pragma unroll
+            for (int q = 0; q < 3 * NP; ++q) atomicAdd(&ga[q], g[q]);
+        }
+    }
+}
+
+// rank-4 update of this thread's own pencil in LDS (no other thread writes it)
+template <typename T>
+__device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T> &nl, T *pencil,
+                                           T half) {
+    for (int c = 0; c < nl.ncol; ++c) {
+        const ColEntry e = nl.cols[c];
+        const T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
+        const T *sc = nl.scale + (int64_t)e.slot * NP;
+        T f[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) f[l] = sc[l] * pa[l] * half;
+        for (int i = 0; i < e.n; ++i) {
+            const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
+            pencil[e.zlo + i] += ch[0] * f[0] + ch[1] * f[1] + ch[2] * f[2] + ch[3] * f[3];
+        }
+    }
+}
+
+template <typename T, int BLOCK, bool GRAD>
+__device__ __forceinline__ void col_zero_next(const ColNL<T> &nl, int nat) {
+    T *pa = nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP;
+    for (int i = threadIdx.x; i < nat * NP; i += BLOCK) pa[i] = (T)0;
+    if constexpr (GRAD) {
+        T *ga = nl.gacc + (int64_t)(nl.par ^ 1) * nl.maxat * 3 * NP;
+        for (int i = threadIdx.x; i < nat * 3 * NP; i += BLOCK) ga[i] = (T)0;
+    }
+}
+
+// local part of prev <- 2 Hs cur - prev (no projector term): D cur - prev,
+// z neighbours from registers, x / y neighbours from the LDS copy of cur
+template <typename T, int E, int R, int ZS, bool DREG>
+__device__ __forceinline__ void local_part(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                           const T (&d)[DREG ? E : 1], int64_t col,
+                                           int64_t plane, int gz0, int n2, const T (&cur)[E],
+                                           T (&prev)[E], const T *lds) {
+    if constexpr (DREG) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
+    } else {
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            int gz = gz0 + z;
+            gz = gz >= n2 ? gz - n2 : gz;
+            const T dz = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+            prev[z] = dz * cur[z] - prev[z];
+        }
+    }
+#pragma unroll
+    for (int p = 1; p <= R; ++p) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            T s = (T)0;
+            if (z + p < E) s += cur[z + p];
+            if (z - p >= 0) s += cur[z - p];
+            prev[z] += c.cz[p] * s;
+        }
+    }
+#pragma unroll
+    for (int p = 1; p <= R; ++p) {
+        axpy_pencil<T, E, ZS>(prev, c.cx[p], lds + c.nb[4 * (p - 1) + 0] * ZS);
+        axpy_pencil<T, E, ZS>(prev, c.cx[p], lds + c.nb[4 * (p - 1) + 1] * ZS);
+        axpy_pencil<T, E, ZS>(prev, c.cy[p], lds + c.nb[4 * (p - 1) + 2] * ZS);
+        axpy_pencil<T, E, ZS>(prev, c.cy[p], lds + c.nb[4 * (p - 1) + 3] * ZS);
+    }
+}
+
+// Same as local_part with a runtime loop over the 4R neighbour pencils, for
+// kernels that keep more pencils resident (the adjoint): one neighbour pencil
+// is in flight at a time instead of all 4R.
+template <typename T, int E, int R, int ZS, bool DREG>
+__device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
+                                                  const StepCtx<T, E, R> &c,
+                                                  const T (&d)[DREG ? E : 1], int64_t col,
+                                                  int64_t plane, int gz0, int n2,
+                                                  const T (&cur)[E], T (&prev)[E],
+                                                  const T *lds) {
+    if constexpr (DREG) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
+    } else {
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            int gz = gz0 + z;
+            gz = gz >= n2 ? gz - n2 : gz;
+            const T dz = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+            prev[z] = dz * cur[z] - prev[z];
+        }
+    }
+#pragma unroll
+    for (int p = 1; p <= R; ++p) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            T s = (T)0;
+            if (z + p < E) s += cur[z + p];
+            if (z - p >= 0) s += cur[z - p];
+            prev[z] += c.cz[p] * s;
+        }
+    }
+    const int tid = threadIdx.x;
+#pragma unroll 1
+    for (int q = 0; q < 4 * R; ++q) {
+        const int p = (q >> 2) + 1, dir = q & 3;
+        int nb;
+        if (dir == 0) nb = (c.active && c.px + p < c.dx) ? tid + p : c.npen;
+        else if (dir == 1) nb = (c.active && c.px - p >= 0) ? tid - p : c.npen;
+        else if (dir == 2) nb = (c.active && c.py + p < c.dy) ? tid + p * c.dx : c.npen;
+        else nb = (c.active && c.py - p >= 0) ? tid - p * c.dx : c.npen;
+        axpy_pencil<T, E, ZS>(prev, c.ncoef[q], lds + nb * ZS);
+    }
+}
+
+// One step with the column projector path (two barriers per step):
+//   A: cur complete in LDS -> projections of cur (own pencil, LDS atomics) and
+//      the local stencil;  B: all reads of cur done -> publish the local part,
+//      add the projector term to the own pencil, reload it.
+// cur is written to LDS at the start even when the previous step left the
+// same values there: a conditional store costs more registers than it saves.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
+          bool LOWREG = false>
+__device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                                const T (&d)[DREG ? E : 1], int64_t col,
+                                                int64_t plane, int gz0, int n2, T (&cur)[E],
+                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first) {
+    if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
+    __syncthreads();
+    if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    if constexpr (LOWREG)
+        local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
+    else
+        local_part<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
+    __syncthreads();
+    if (first) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) prev[z] *= (T)0.5;
+    }
+    if constexpr (MASKZ) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) prev[z] = (z < c.dz) ? prev[z] : (T)0;
+    }
+    if (c.nat) {
+        if (c.active) store_pencil<T, E, ZS>(c.mine, prev);
+        if (nl.ncol) col_update<T>(a, nl, c.mine, first ? (T)0.5 : (T)1);
+        if (c.active) load_pencil<T, E, ZS>(c.mine, prev);
+        col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
+    }
+    nl.par ^= 1;
+}
+
+// projections of one vector without a recurrence step (column path)
+template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD>
+__device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                              const T (&vec)[E], ColNL<T> &nl) {
+    if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
+    __syncthreads();
+    if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    __syncthreads();
+    col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
+    nl.par ^= 1;
 }
 
 template <typename T, int E>

@@ -97,6 +97,8 @@ class Context:
             moment_sum = torch.empty(self.K + 1, dtype=torch.float64, device=dev)
         L.sq_density(self.ctx, _ptr(V), float(lambda_min), float(lambda_max), _ptr(moments),
                      _ptr(moment_sum), _stream())
+        # sq_fermi_level contracts these moments later: keep the buffer alive
+        self._moments = moments
         return moments, moment_sum
 
     def fermi_level(self, Ne: float = 0.0, tol: float = 1e-10, max_iter: int = 200,
