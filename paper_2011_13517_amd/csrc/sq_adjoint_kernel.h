@@ -44,14 +44,14 @@ __device__ __forceinline__ void ck_store(T *ck, bool active, int tid, int cidx, 
                                          const T (&vec)[E]) {
     if (!active) return;
 #pragma unroll
-    for (int z = 0; z < E; ++z) ck[((int64_t)(cidx * 2 + which) * E + z) * (E * E) + tid] = vec[z];
+    for (int z = 0; z < E; ++z) sgpr_ptr(ck + ((int64_t)(cidx * 2 + which) * E + z) * (E * E))[(uint32_t)tid] = vec[z];
 }
 template <typename T, int E>
 __device__ __forceinline__ void ck_load(const T *ck, bool active, int tid, int cidx, int which,
                                         T (&vec)[E]) {
     if (!active) return;
 #pragma unroll
-    for (int z = 0; z < E; ++z) vec[z] = ck[((int64_t)(cidx * 2 + which) * E + z) * (E * E) + tid];
+    for (int z = 0; z < E; ++z) vec[z] = sgpr_ptr(ck + ((int64_t)(cidx * 2 + which) * E + z) * (E * E))[(uint32_t)tid];
 }
 
 // LDS tables of the atoms of the current box used by the reverse sweep
@@ -196,44 +196,43 @@ __device__ __forceinline__ void adjoint_rstep_col(const AdjointArgs<T> &aa,
 }
 
 // Reverse step when the forward pass stored every v_k (checkpoint stride 1):
-// cur <- v_k from HBM, G += alpha vt_{k+1} v_k, tb <- vt_k; only the adjoint
-// recurrence applies Hs, so four pencils are resident instead of five.
+// G += alpha vt_{k+1} v_k and tb <- vt_k.  v_k is read from its HBM slot where
+// it is used (the G update, its projections for dR) instead of being held as a
+// register pencil, so only vt_{k+1}, vt_{k+2} and G stay resident.
 template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD>
 __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
                                                  const StepCtx<T, E, R> &c, const AdjNode &nd,
                                                  const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
                                                  ColNL<T> &nlB, const Slot *slots,
                                                  double (*dRacc)[3], const T *ck, int k,
-                                                 T (&cur)[E], T (&ta)[E], T (&tb)[E], T (&G)[E],
-                                                 double tau) {
+                                                 T (&ta)[E], T (&tb)[E], T (&G)[E], double tau) {
     const RegionArgs<T> &a = aa.g;
-    const int tid = threadIdx.x;
+    constexpr int EE = E * E;
+    const T *vk = ck + (int64_t)k * E * EE + threadIdx.x;
+    const T alpha = k == 0 ? (T)1 : (T)2;
     if (c.active) {
 #pragma unroll
-        for (int z = 0; z < E; ++z) cur[z] = ck[((int64_t)k * E + z) * (E * E) + tid];
+        for (int z = 0; z < E; ++z)
+            G[z] += alpha * ta[z] * sgpr_ptr(ck + ((int64_t)k * E + z) * EE)[threadIdx.x];
     }
-    const T alpha = k == 0 ? (T)1 : (T)2;
-#pragma unroll
-    for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * cur[z];
     if (k >= 1) {
-        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
-            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false);
+        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true, GRAD>(
+            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false, &nlB, vk, EE);
         if (nd.is_ctr) {
             const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
 #pragma unroll
             for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
         }
     } else {
-        if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, ta, nlA);
+        if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD, true>(a, c, ta, nlA, &nlB, vk, EE);
     }
     if constexpr (GRAD) {
-        col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, cur, nlB);
         const double f = (double)alpha * a.h3 / tau;
         const T *dA = nlA.pacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * NP;
         const T *gA = nlA.gacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * 3 * NP;
         const T *dB = nlB.pacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * NP;
         const T *gB = nlB.gacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * 3 * NP;
-        for (int j = tid; j < c.nat; j += BLOCK) {
+        for (int j = threadIdx.x; j < c.nat; j += BLOCK) {
             const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
@@ -428,10 +427,10 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             }
             for (int k = K - 1; k >= 0; k -= 2) {
                 adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
-                    aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k, v, t1, t2, G, tau);
+                    aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k, t1, t2, G, tau);
                 if (k - 1 >= 0)
                     adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
-                        aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k - 1, v, t2, t1, G, tau);
+                        aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k - 1, t2, t1, G, tau);
             }
         } else {
             // ---- forward: v_0 .. v_K, checkpoints (v_cC, v_cC+1) for cC+1 <= K-1 ----

@@ -34,6 +34,23 @@ constexpr int max_atoms_in_region() {
     return n > 128 ? 128 : (n < 0 ? 0 : n);
 }
 
+// A block-uniform pointer pinned in scalar registers.  Per-z loads of a
+// pencil then address as (SGPR base) + (32-bit thread offset); without the pin
+// the compiler folds the thread offset into E hoisted 64-bit VGPR addresses
+// and spills them in the large-region kernels.
+// The result is a global (address space 1) pointer so that the accesses
+// stay global loads and stores rather than flat ones.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ global_ptr<T> sgpr_ptr(T *p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<global_ptr<T>>(((uint64_t)hi << 32) | lo);
+}
+
 template <typename T, int E, int ZS>
 __device__ __forceinline__ void store_pencil(T *dst, const T (&v)[E]) {
     if constexpr (sizeof(T) == 4 && ZS % 4 == 0) {
@@ -272,7 +289,7 @@ __device__ __forceinline__ void region_step(const RegionArgs<T> &a, const StepCt
         for (int z = 0; z < E; ++z) {
             int gz = gz0 + z;
             gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
             prev[z] = dz * cur[z] - prev[z];
         }
     }
@@ -351,9 +368,10 @@ __device__ __forceinline__ int build_columns(const RegionArgs<T> &a, const Slot 
 
 // raw projections of this thread's pencil (in LDS) onto the crossing supports,
 // reduced over the box with LDS atomics into the current parity buffer
+// (pencil z stride zs: 1 for the LDS copy, E^2 for a stored vector in HBM)
 template <typename T, bool GRAD>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
-                                         const T *pencil) {
+                                         const T *pencil, int zs = 1) {
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         T s[NP] = {0, 0, 0, 0};
@@ -363,7 +381,7 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
             for (int i = 0; i < 3 * NP; ++i) g[i] = 0;
         }
         for (int i = 0; i < e.n; ++i) {
-            const T v = pencil[e.zlo + i];
+            const T v = pencil[(int64_t)(e.zlo + i) * zs];
             const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
 #pragma unroll
             for (int l = 0; l < NP; ++l) s[l] += ch[l] * v;
@@ -427,7 +445,7 @@ __device__ __forceinline__ void local_part(const RegionArgs<T> &a, const StepCtx
         for (int z = 0; z < E; ++z) {
             int gz = gz0 + z;
             gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
             prev[z] = dz * cur[z] - prev[z];
         }
     }
@@ -468,7 +486,7 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
         for (int z = 0; z < E; ++z) {
             int gz = gz0 + z;
             gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
             prev[z] = dz * cur[z] - prev[z];
         }
     }
@@ -501,15 +519,22 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
 //      add the projector term to the own pencil, reload it.
 // cur is written to LDS at the start even when the previous step left the
 // same values there: a conditional store costs more registers than it saves.
+// With XDOTS the same window also projects a second vector xv (a stored v_k,
+// z stride xzs) into the state xnl, which then advances its parity too.
 template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
-          bool LOWREG = false>
+          bool LOWREG = false, bool XDOTS = false>
 __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
                                                 const T (&d)[DREG ? E : 1], int64_t col,
                                                 int64_t plane, int gz0, int n2, T (&cur)[E],
-                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first) {
+                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first,
+                                                ColNL<T> *xnl = nullptr, const T *xv = nullptr,
+                                                int xzs = 1) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    if constexpr (XDOTS) {
+        if (xnl->ncol) col_dots<T, GRAD>(a, *xnl, xv, xzs);
+    }
     if constexpr (LOWREG)
         local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
     else
@@ -528,20 +553,31 @@ __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const St
         if (nl.ncol) col_update<T>(a, nl, c.mine, first ? (T)0.5 : (T)1);
         if (c.active) load_pencil<T, E, ZS>(c.mine, prev);
         col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
+        if constexpr (XDOTS) col_zero_next<T, BLOCK, GRAD>(*xnl, c.nat);
     }
     nl.par ^= 1;
+    if constexpr (XDOTS) xnl->par ^= 1;
 }
 
 // projections of one vector without a recurrence step (column path)
-template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD>
+template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD, bool XDOTS = false>
 __device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
-                                              const T (&vec)[E], ColNL<T> &nl) {
+                                              const T (&vec)[E], ColNL<T> &nl,
+                                              ColNL<T> *xnl = nullptr, const T *xv = nullptr,
+                                              int xzs = 1) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    if constexpr (XDOTS) {
+        if (xnl->ncol) col_dots<T, GRAD>(a, *xnl, xv, xzs);
+    }
     __syncthreads();
     col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
     nl.par ^= 1;
+    if constexpr (XDOTS) {
+        col_zero_next<T, BLOCK, GRAD>(*xnl, c.nat);
+        xnl->par ^= 1;
+    }
 }
 
 template <typename T, int E>
