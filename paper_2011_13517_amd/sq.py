@@ -97,20 +97,27 @@ class Context:
             moment_sum = torch.empty(self.K + 1, dtype=torch.float64, device=dev)
         L.sq_density(self.ctx, _ptr(V), float(lambda_min), float(lambda_max), _ptr(moments),
                      _ptr(moment_sum), _stream())
+        self.generation = getattr(self, "generation", 0) + 1
         # sq_fermi_level contracts these moments later: keep the buffer alive
+        # (the generation counter lets SQDensity detect a stale backward)
         self._moments = moments
         return moments, moment_sum
 
     def fermi_level(self, Ne: float = 0.0, tol: float = 1e-10, max_iter: int = 200,
                     lambda_f: Optional[torch.Tensor] = None, want_fields: bool = True,
-                    device=None):
-        """sq_fermi_level: (lambda_f[1], rho[n], u[n], totals[8]) on the device."""
+                    device=None, rho: Optional[torch.Tensor] = None,
+                    u: Optional[torch.Tensor] = None, totals: Optional[torch.Tensor] = None):
+        """sq_fermi_level: (lambda_f[1], rho[n], u[n], totals[8]) on the device
+        (outputs are allocated unless given)."""
         dev = device or torch.device("cuda")
         if lambda_f is None:
             lambda_f = torch.zeros(1, dtype=torch.float64, device=dev)
-        rho = torch.empty(self.n_nodes, dtype=torch.float64, device=dev) if want_fields else None
-        u = torch.empty(self.n_nodes, dtype=torch.float64, device=dev) if want_fields else None
-        totals = torch.empty(8, dtype=torch.float64, device=dev)
+        if want_fields and rho is None:
+            rho = torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+        if want_fields and u is None:
+            u = torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+        if totals is None:
+            totals = torch.empty(8, dtype=torch.float64, device=dev)
         L.sq_fermi_level(self.ctx, float(Ne), float(tol), int(max_iter), _ptr(lambda_f),
                          _ptr(rho), _ptr(u), _ptr(totals), _stream())
         return lambda_f, rho, u, totals
@@ -134,3 +141,55 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class SQDensity(torch.autograd.Function):
+    """(V, R) -> (rho, u, lambda_f) through the HIP library, differentiable in V and R.
+
+    forward: sq_density (device Lanczos bounds unless given) and sq_fermi_level.
+    backward: sq_density_backward, i.e. the adjoint of the Chebyshev recurrence
+    (Eqs. (Chebyshev), (rhoq), (uq)) at fixed lambda_f, omega and tau: the
+    returned dV and dR are partial derivatives with the Fermi level held fixed;
+    the cotangent of lambda_f is not propagated.
+
+    R is a [n_atoms, 3] tensor standing for the atom positions the projector
+    tables of the context were built at; the forward pass does not read its
+    values, the backward pass returns dy/dR_J through chi(x - R_J).
+
+        rho, u, lam = SQDensity.apply(V, R, context, Ne, tol, max_iter)
+    """
+
+    @staticmethod
+    def forward(fctx, V, R, context: "Context", Ne: float = 0.0, tol: float = 1e-10,
+                max_iter: int = 200, bounds=(math.nan, math.nan),
+                lambda_f: Optional[torch.Tensor] = None):
+        _dev(V)
+        context.density(V, float(bounds[0]), float(bounds[1]))
+        lam = lambda_f.clone() if lambda_f is not None else None
+        lam, rho, u, totals = context.fermi_level(Ne=Ne, tol=tol, max_iter=max_iter,
+                                                  lambda_f=lam, device=V.device)
+        fctx.context = context
+        fctx.generation = context.generation
+        fctx.V_shape = V.shape
+        fctx.has_R = R is not None
+        fctx.mark_non_differentiable(lam)
+        fctx.totals = totals
+        return rho, u, lam
+
+    @staticmethod
+    def backward(fctx, g_rho, g_u, g_lam):
+        context = fctx.context
+        if context.generation != fctx.generation:
+            raise RuntimeError("SQDensity.backward: the context ran another forward pass since "
+                               "this one; the adjoint needs the state of its own forward pass")
+        dev = g_rho.device if g_rho is not None else g_u.device
+        gr = g_rho.contiguous() if g_rho is not None else None
+        gu = g_u.contiguous() if g_u is not None else None
+        dV = torch.zeros(fctx.V_shape, dtype=torch.float64, device=dev) \
+            if fctx.needs_input_grad[0] else None
+        dR = None
+        if fctx.has_R and fctx.needs_input_grad[1] and context.n_atoms:
+            dR = torch.zeros((context.n_atoms, 3), dtype=torch.float64, device=dev)
+        if dV is not None or dR is not None:
+            context.backward(gr, gu, dV, dR)
+        return (dV, dR) + (None,) * 7
