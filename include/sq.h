@@ -81,6 +81,11 @@ typedef struct {
                          /* SQ_FP64: the gradient sums cancel strongly, so FP32      */
                          /* vectors lose ~1e-4 relative at K ~ 80; FP64 adjoint      */
                          /* supports region edges <= 21, FP32 adjoint edges <= 27)   */
+    int32_t tune;        /* launch plan when regions fall in several edge buckets   */
+                         /* (9, 13, 17, 21, 27, 32): 0 = sq_setup times one launch   */
+                         /* at the largest bucket against one launch per bucket on   */
+                         /* a sample of the regions and keeps the faster (cached per */
+                         /* geometry in the process); 1 = one launch per bucket      */
 } sq_params;
 
 /* Nonlocal Kleinman-Bylander projectors (Section 2.1, the nonlocal operator
@@ -108,6 +113,7 @@ typedef struct {
     int32_t max_region[3];  /* largest region box                                      */
     int64_t region_points;  /* sum over nodes of the region size |R_q|                 */
     int64_t workspace_bytes;/* device memory held by the context                       */
+    int32_t n_launches;     /* persistent region launches per pass (the launch plan)   */
 } sq_info;
 
 /* Builds a context: validates parameters, builds the region work list and

@@ -28,7 +28,7 @@ class sq_params(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double * 3), ("fd_order", C.c_int32),
                 ("bc", C.c_int32), ("rcut", C.c_int32 * 3), ("order", C.c_int32),
                 ("kT", C.c_double), ("precision", C.c_int32), ("ckpt_every", C.c_int32),
-                ("adjoint_precision", C.c_int32)]
+                ("adjoint_precision", C.c_int32), ("tune", C.c_int32)]
 
 
 class sq_projectors(C.Structure):
@@ -40,7 +40,8 @@ class sq_projectors(C.Structure):
 class sq_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("order", C.c_int32), ("vgrid", C.c_int32 * 3),
                 ("n_atoms", C.c_int32), ("max_region", C.c_int32 * 3),
-                ("region_points", C.c_int64), ("workspace_bytes", C.c_int64)]
+                ("region_points", C.c_int64), ("workspace_bytes", C.c_int64),
+                ("n_launches", C.c_int32)]
 
 
 class SQError(RuntimeError):

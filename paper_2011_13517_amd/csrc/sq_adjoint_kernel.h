@@ -197,53 +197,88 @@ __device__ __forceinline__ void adjoint_rstep_col(const AdjointArgs<T> &aa,
 
 // Reverse step when the forward pass stored every v_k (checkpoint stride 1):
 // G += alpha vt_{k+1} v_k and tb <- vt_k.  v_k is read from its HBM slot where
-// it is used (the G update, its projections for dR) instead of being held as a
-// register pencil, so only vt_{k+1}, vt_{k+2} and G stay resident.
-template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD>
+// it is used (the G update) instead of being held as a register pencil, so only
+// vt_{k+1}, vt_{k+2} and G stay resident; the projections of v_k needed for dR
+// were stored by the forward sweep next to the vectors.
+// With GHBM the accumulator G lives in the slot (gb, [z][pencil], L2-resident)
+// and is updated in chunks of loads then stores, instead of in registers.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD, bool GHBM>
 __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
                                                  const StepCtx<T, E, R> &c, const AdjNode &nd,
                                                  const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
-                                                 ColNL<T> &nlB, const Slot *slots,
-                                                 double (*dRacc)[3], const T *ck, int k,
-                                                 T (&ta)[E], T (&tb)[E], T (&G)[E], double tau) {
+                                                 const Slot *slots, double (*dRacc)[3],
+                                                 const T *ck, T *gb, int k, T (&ta)[E],
+                                                 T (&tb)[E], T (&G)[GHBM ? 1 : E], double tau) {
     const RegionArgs<T> &a = aa.g;
     constexpr int EE = E * E;
-    const T *vk = ck + (int64_t)k * E * EE + threadIdx.x;
     const T alpha = k == 0 ? (T)1 : (T)2;
     if (c.active) {
+        const uint32_t t = threadIdx.x;
+        if constexpr (GHBM) {
+            constexpr int CH = 9;
 #pragma unroll
-        for (int z = 0; z < E; ++z)
-            G[z] += alpha * ta[z] * sgpr_ptr(ck + ((int64_t)k * E + z) * EE)[threadIdx.x];
+            for (int z0 = 0; z0 < E; z0 += CH) {
+                T vk[CH], g[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    if (z0 + i < E) {
+                        vk[i] = sgpr_ptr(ck + ((int64_t)k * E + z0 + i) * EE)[t];
+                        g[i] = sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (z0 + i < E) sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t] = g[i] + alpha * ta[z0 + i] * vk[i];
+            }
+        } else {
+#pragma unroll
+            for (int z = 0; z < E; ++z)
+                G[z] += alpha * ta[z] * sgpr_ptr(ck + ((int64_t)k * E + z) * EE)[t];
+        }
     }
     if (k >= 1) {
-        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true, GRAD>(
-            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false, &nlB, vk, EE);
+        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
+            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false);
         if (nd.is_ctr) {
             const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
 #pragma unroll
             for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
         }
     } else {
-        if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD, true>(a, c, ta, nlA, &nlB, vk, EE);
+        if constexpr (GRAD) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, ta, nlA);
     }
     if constexpr (GRAD) {
         const double f = (double)alpha * a.h3 / tau;
         const T *dA = nlA.pacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * NP;
         const T *gA = nlA.gacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * 3 * NP;
-        const T *dB = nlB.pacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * NP;
-        const T *gB = nlB.gacc + (int64_t)(nlB.par ^ 1) * nlB.maxat * 3 * NP;
+        const T *pk = ck + (int64_t)a.K * E * EE + (int64_t)k * MAX_REGION_ATOMS * 4 * NP;
         for (int j = threadIdx.x; j < c.nat; j += BLOCK) {
             const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+            const T *pj = pk + j * 4 * NP;
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
                 double s = 0.0;
 #pragma unroll
                 for (int l = 0; l < NP; ++l)
-                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)dB[j * NP + l] +
-                                  (double)dA[j * NP + l] * (double)gB[(j * NP + l) * 3 + x]);
+                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)pj[l] +
+                                  (double)dA[j * NP + l] * (double)pj[NP + l * 3 + x]);
                 dRacc[j][x] += f * s;
             }
         }
+    }
+}
+
+// copy the projections of the vector the last step projected (parity buffer
+// par ^ 1 of nl) into the store-all slot, row k
+template <typename T, int BLOCK>
+__device__ __forceinline__ void store_projections(const ColNL<T> &nl, int nat, T *ck, int K,
+                                                  int E3, int k) {
+    T *pk = ck + (int64_t)K * E3 + (int64_t)k * MAX_REGION_ATOMS * 4 * NP;
+    const T *pa = nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP;
+    const T *ga = nl.gacc + (int64_t)(nl.par ^ 1) * nl.maxat * 3 * NP;
+    for (int i = threadIdx.x; i < nat * 4 * NP; i += BLOCK) {
+        const int j = i / (4 * NP), q = i - j * 4 * NP;
+        pk[i] = q < NP ? pa[j * NP + q] : ga[j * 3 * NP + (q - NP)];
     }
 }
 
@@ -265,6 +300,10 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
     constexpr int CA = COLNL ? AT : 1;
     constexpr int CG = (COLNL && GRAD) ? AT : 1;
     constexpr bool DREG = sizeof(T) == 4 ? E <= 21 : E <= 13;
+    // store-all kernels with dR whose pencils do not fit the registers keep the
+    // dV accumulator in their slot instead
+    constexpr bool GHBM = COLNL && STOREALL && GRAD &&
+                          ((sizeof(T) == 4 && E >= 27) || (sizeof(T) == 8 && E >= 17));
     constexpr int EE = E * E;
     const RegionArgs<T> &a = aa.g;
 
@@ -395,7 +434,8 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             __syncthreads();
         }
 
-        T v[E], G[E];
+        T v[E], G[GHBM ? 1 : E];
+        T *gb = ck + storeall_slot_elems(K, E) - (int64_t)E * E * E;
         if constexpr (COLNL && STOREALL) {
             // ---- forward storing v_0 .. v_{K-1}; reverse reads them back ----
             T w[E];
@@ -405,17 +445,27 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                 w[z] = (T)0;
             }
             // slot layout [k][z][pencil]: a wave's stores coalesce
-            // (v_K itself is never needed by the reverse sweep)
+            // (v_K itself is never needed by the reverse sweep).  With GRAD the
+            // step's projections of v_k (chi and dchi/dR) go to the slot too.
+            constexpr int E3 = E * E * E;
             ck_store<T, E>(ck, c.active, tid, 0, 0, v);
             for (int k = 0; k + 1 <= K - 1; k += 2) {
-                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
                     a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0);
                 ck_store<T, E>(ck, c.active, tid, 0, k + 1, w);
+                if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k);
                 if (k + 2 <= K - 1) {
-                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true>(
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
                         a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false);
                     ck_store<T, E>(ck, c.active, tid, 0, k + 2, v);
+                    if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k + 1);
                 }
+            }
+            if constexpr (GRAD) {
+                // projections of v_{K-1}, the last stored vector
+                if ((K - 1) % 2 == 0) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, v, nlB);
+                else col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, w, nlB);
+                store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, K - 1);
             }
             T t1[E], t2[E];
             const T aK = (T)(2.0 * (nd.gr * aa.coef_c[K] + nd.gu * aa.coef_d[K]));
@@ -423,14 +473,18 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             for (int z = 0; z < E; ++z) {
                 t1[z] = (is_ctr && z == cz0) ? aK : (T)0;
                 t2[z] = (T)0;
-                G[z] = (T)0;
+                if constexpr (GHBM) {
+                    if (c.active) sgpr_ptr(gb + (int64_t)z * EE)[(uint32_t)tid] = (T)0;
+                } else {
+                    G[z] = (T)0;
+                }
             }
             for (int k = K - 1; k >= 0; k -= 2) {
-                adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
-                    aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k, t1, t2, G, tau);
+                adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
+                    aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k, t1, t2, G, tau);
                 if (k - 1 >= 0)
-                    adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
-                        aa, c, nd, d, lds, nlA, nlB, slots, cdR, ck, k - 1, t2, t1, G, tau);
+                    adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
+                        aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k - 1, t2, t1, G, tau);
             }
         } else {
             // ---- forward: v_0 .. v_K, checkpoints (v_cC, v_cC+1) for cC+1 <= K-1 ----
@@ -514,7 +568,10 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                 if (z < c.dz) {
                     int gz = gz0 + z;
                     gz = gz >= n2 ? gz - n2 : gz;
-                    unsafeAtomicAdd(aa.dV + col + plane * gz, (double)G[z] * itau);
+                    T gz_val;
+                    if constexpr (GHBM) gz_val = sgpr_ptr(gb + (int64_t)z * EE)[(uint32_t)tid];
+                    else gz_val = G[z];
+                    unsafeAtomicAdd(aa.dV + col + plane * gz, (double)gz_val * itau);
                 }
             }
         }

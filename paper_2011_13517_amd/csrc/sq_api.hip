@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -58,6 +60,47 @@ void fd_weights(int r, double *w) {
 
 }  // namespace
 
+// A launch group: a contiguous range of the sorted work list run by one
+// persistent kernel instantiated for edge bucket E.
+struct Group {
+    int E = 0;
+    bool maskz = false;
+    int begin = 0, count = 0;
+    int grid_fwd = 1, grid_adj = 1;
+};
+enum { PLAN_MERGED = 0, PLAN_SPLIT = 1 };
+
+static int item_bucket(const Item &it) {
+    return edge_bucket(std::max(it.dim[0], std::max(it.dim[1], it.dim[2])));
+}
+
+// groups of a sorted work list: one group at the largest bucket (merged), or
+// one group per edge bucket (split)
+static std::vector<Group> make_groups(const std::vector<Item> &items, int plan) {
+    std::vector<Group> g;
+    const int n = (int)items.size();
+    for (int i = 0; i < n;) {
+        Group gr;
+        gr.begin = i;
+        gr.E = item_bucket(items[i]);
+        int j = i;
+        while (j < n && (plan == PLAN_MERGED || item_bucket(items[j]) == gr.E)) {
+            gr.E = std::max(gr.E, item_bucket(items[j]));
+            ++j;
+        }
+        gr.count = j - i;
+        for (int q = i; q < j; ++q)
+            if (items[q].dim[2] != gr.E) gr.maskz = true;
+        g.push_back(gr);
+        i = j;
+    }
+    return g;
+}
+
+// plans measured by the tuner, per geometry (process-wide)
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
 struct sq_ctx {
     sq_params p{};
     int r = 1;
@@ -70,9 +113,9 @@ struct sq_ctx {
     int K = 0;
     int prec = 0;
     int aprec = 0;   // precision of the adjoint
-    int E = 0;
-    bool maskz = false;
-    int grid_fwd = 1;
+    int E = 0;                    // largest edge bucket of the work list
+    std::vector<Group> groups;    // launch plan: one persistent launch per group
+    int plan = 0;                 // PLAN_MERGED or PLAN_SPLIT
     int max_region[3] = {};
     int64_t region_points = 0;
     int64_t bytes = 0;
@@ -109,7 +152,6 @@ struct sq_ctx {
     // adjoint
     bool adj_ok = false;
     bool storeall = false;
-    int grid_adj = 1;
     int n_ckpt = 1;
     int64_t ckpt_stride = 0;
     void *d_ckpt = nullptr;
@@ -172,6 +214,7 @@ sq_status validate(const sq_params *p) {
     if (p->ckpt_every < 0) return fail(SQ_ERR_ARG, "ckpt_every must be >= 0");
     if (p->adjoint_precision != SQ_FP64 && p->adjoint_precision != SQ_FP32_ACC64)
         return fail(SQ_ERR_ARG, "adjoint_precision %d unknown", p->adjoint_precision);
+    if (p->tune != 0 && p->tune != 1) return fail(SQ_ERR_ARG, "tune %d unknown", p->tune);
     return SQ_OK;
 }
 
@@ -205,6 +248,142 @@ void ring_bbox(std::vector<int> &c, int n, bool periodic, int *lo, int *dim) {
     int mx = 0;
     for (int x : c) mx = std::max(mx, ((x - best_end) % n + n) % n);
     *dim = mx + 1;
+}
+
+template <typename T>
+void fill_region_args(const sq_ctx &c, RegionArgs<T> &a) {
+    for (int x = 0; x < 3; ++x) {
+        a.N[x] = c.N[x];
+        a.ih2[x] = c.ih2[x];
+    }
+    a.periodic = c.periodic;
+    a.scal = c.d_scal;
+    for (int p = 0; p <= MAX_R; ++p) a.w[p] = c.w[p];
+    a.h3 = c.h3;
+    a.K = c.K;
+    a.n_atoms = c.n_atoms;
+    a.atoms = c.d_atoms;
+    a.sup_pack = c.d_pack;
+    a.colidx = c.d_colidx;
+    a.cJ = c.d_cJ;
+    a.status = c.d_status;
+    if constexpr (sizeof(T) == 8) {
+        a.D = c.d_D64;
+        a.chi = c.d_chi64;
+        a.dchi = c.d_dchi64;
+    } else {
+        a.D = c.d_D32;
+        a.chi = c.d_chi32;
+        a.dchi = c.d_dchi32;
+    }
+}
+
+// forward recurrence of every group of a plan (one persistent launch each,
+// its own work counter)
+template <typename T>
+sq_status run_forward_t(const sq_ctx &c, const std::vector<Group> &groups, const Item *items,
+                        double *mu, hipStream_t st) {
+    HIP_TRY(k_fill_i32(c.d_counter, 0, (int64_t)groups.size(), st));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        RegionArgs<T> a{};
+        fill_region_args(c, a);
+        a.items = items + groups[g].begin;
+        a.n_items = groups[g].count;
+        a.counter = c.d_counter + g;
+        a.moments = mu;
+        HIP_TRY(launch_forward(c.prec, groups[g].E, c.r, groups[g].maskz, &a, groups[g].grid_fwd, st));
+    }
+    return SQ_OK;
+}
+
+sq_status run_forward(const sq_ctx &c, const std::vector<Group> &groups, const Item *items,
+                      double *mu, hipStream_t st) {
+    return c.prec == SQ_FP64 ? run_forward_t<double>(c, groups, items, mu, st)
+                             : run_forward_t<float>(c, groups, items, mu, st);
+}
+
+// Launch-plan tuner: times the merged and the split plan of the work list on
+// an evenly strided sample of at most 8192 regions (same bucket mix), with a
+// zero potential (the cost does not depend on the values), and keeps the
+// faster.  Results are cached per geometry key for the process.
+sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
+    std::string key;
+    {
+        std::map<int, int64_t> hist;
+        for (const Item &it : items) hist[item_bucket(it)] += 1;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "p%d r%d K%d a%d n%d bc%d", c.prec, c.r, c.K, c.n_atoms,
+                      (int)items.size(), c.p.bc);
+        key = buf;
+        for (auto &kv : hist) key += " " + std::to_string(kv.first) + ":" + std::to_string(kv.second);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto f = g_tune_cache.find(key);
+        if (f != g_tune_cache.end()) {
+            c.plan = f->second;
+            return SQ_OK;
+        }
+    }
+    const int n = (int)items.size();
+    const int stride = std::max(1, n / 8192);
+    std::vector<Item> sample;
+    for (int i = 0; i < n; i += stride) {
+        Item it = items[i];
+        it.out = (int32_t)sample.size();
+        sample.push_back(it);
+    }
+    Item *d_sample = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d_sample), sample.size() * sizeof(Item)) != hipSuccess)
+        return fail(SQ_ERR_OOM, "tuner: hipMalloc failed");
+    std::vector<Group> plans[2] = {make_groups(sample, PLAN_MERGED), make_groups(sample, PLAN_SPLIT)};
+    for (auto &gs : plans)
+        for (Group &g : gs) {
+            const int occ = forward_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
+            g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+        }
+    Scalars s{};
+    s.omega = 0.0;
+    s.tau = 1.0;
+    float best = -1.0f;
+    int best_plan = PLAN_SPLIT;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    sq_status st = SQ_OK;
+    if (hipMemcpy(d_sample, sample.data(), sample.size() * sizeof(Item), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c.d_scal, &s, sizeof(s), hipMemcpyHostToDevice) != hipSuccess ||
+        (c.d_D64 && hipMemset(c.d_D64, 0, c.nv * sizeof(double)) != hipSuccess) ||
+        (c.d_D32 && hipMemset(c.d_D32, 0, c.nv * sizeof(float)) != hipSuccess) ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = fail(SQ_ERR_HIP, "tuner setup failed");
+    }
+    for (int pl = 0; pl < 2 && st == SQ_OK; ++pl) {
+        // one untimed run, then one timed
+        st = run_forward(c, plans[pl], d_sample, c.d_mu, nullptr);
+        if (st == SQ_OK && hipEventRecord(e0, nullptr) != hipSuccess) st = fail(SQ_ERR_HIP, "event");
+        if (st == SQ_OK) st = run_forward(c, plans[pl], d_sample, c.d_mu, nullptr);
+        float ms = 0.0f;
+        if (st == SQ_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = fail(SQ_ERR_HIP, "tuner timing failed");
+        if (st == SQ_OK && (best < 0.0f || ms < best)) {
+            best = ms;
+            best_plan = pl == 0 ? PLAN_MERGED : PLAN_SPLIT;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(d_sample);
+    if (hipMemset(c.d_scal, 0, sizeof(Scalars)) != hipSuccess ||
+        hipMemset(c.d_status, 0, sizeof(int32_t)) != hipSuccess)
+        return fail(SQ_ERR_HIP, "tuner reset failed");
+    if (st != SQ_OK) return st;
+    c.plan = best_plan;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_plan;
+    return SQ_OK;
 }
 
 }  // namespace
@@ -299,16 +478,16 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         return bail(fail(SQ_ERR_ARG, "region edge %d exceeds the supported %d for this precision",
                          emax, max_edge(c.prec)));
     c.E = edge_bucket(emax);
-    c.maskz = false;
     bool uniform = true;
     for (const Item &it : items) {
-        if (it.dim[2] != c.E) c.maskz = true;
         if (it.dim[0] != items[0].dim[0] || it.dim[1] != items[0].dim[1] ||
             it.dim[2] != items[0].dim[2])
             uniform = false;
     }
-    if (!uniform) {   // largest regions first (longest-processing-time order)
+    if (!uniform) {   // by edge bucket, then largest regions first (LPT order)
         std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+            const int ea = item_bucket(a), eb = item_bucket(b);
+            if (ea != eb) return ea > eb;
             return (int64_t)a.dim[0] * a.dim[1] * a.dim[2] > (int64_t)b.dim[0] * b.dim[1] * b.dim[2];
         });
     }
@@ -450,7 +629,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         if ((st = c.upload(&(ptr), (src), (n))) != SQ_OK) return bail(st);  \
     } while (0)
     UPLOAD(c.d_items, items.data(), items.size());
-    ALLOC(c.d_counter, 4);
+    ALLOC(c.d_counter, 64);
     ALLOC(c.d_status, 4);
     ALLOC(c.d_scal, 1);
     if (c.prec == SQ_FP64 || c.aprec == SQ_FP64) ALLOC(c.d_D64, c.nv);
@@ -529,33 +708,67 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         hipMemset(c.d_status, 0, sizeof(int32_t)) != hipSuccess ||
         hipMemset(c.d_scal, 0, sizeof(Scalars)) != hipSuccess)
         return bail(fail(SQ_ERR_HIP, "hipMemset failed"));
-    const int occ = forward_blocks_per_cu(c.prec, c.E, c.r, c.maskz);
-    c.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, c.n_items));
-    // adjoint: one checkpoint slot per resident workgroup
-    c.adj_ok = c.E <= adjoint_max_edge(c.aprec);
+    // ---- launch plan -----------------------------------------------------
+    // Regions of several edge buckets run either as one launch at the largest
+    // bucket (small boxes leave most of a large workgroup idle) or as one
+    // launch per bucket (more launches, each with its own tail).  With
+    // params->tune == 0 both plans are timed here on a sample of the work
+    // list and the faster one is kept (cached per geometry); otherwise the
+    // split plan is used whenever there is more than one bucket.
+    auto grids = [&](std::vector<Group> &gs) {
+        for (Group &g : gs) {
+            const int occ = forward_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
+            g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+        }
+    };
+    std::vector<Group> merged = make_groups(items, PLAN_MERGED);
+    std::vector<Group> split = make_groups(items, PLAN_SPLIT);
+    if ((int)split.size() > 64) return bail(fail(SQ_ERR_ARG, "too many launch groups"));
+    grids(merged);
+    grids(split);
+    c.plan = split.size() > 1 ? PLAN_SPLIT : PLAN_MERGED;
+    if (split.size() > 1 && c.p.tune == 0) {
+        const sq_status ts = tune_plan(c, items, ncu);
+        if (ts != SQ_OK) return bail(ts);
+    }
+    c.groups = c.plan == PLAN_SPLIT ? split : merged;
+
+    // adjoint: one vector slot per resident workgroup, shared by the groups
+    c.adj_ok = true;
+    for (const Group &g : c.groups) c.adj_ok = c.adj_ok && g.E <= adjoint_max_edge(c.aprec);
     if (c.adj_ok) {
         const bool grad = c.n_atoms > 0 && c.have_dchi;
-        const int64_t e3 = (int64_t)c.E * c.E * c.E;
         const int64_t esz = c.aprec == SQ_FP64 ? 8 : 4;
+        auto agrid = [&](const Group &g, bool sa) {
+            const int occ = adjoint_blocks_per_cu(c.aprec, g.E, c.r, sa, grad);
+            return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+        };
         // stride 1 keeps every v_k of the in-flight regions (no rebuild, two
         // operator applications per step); chosen by default when that pool
         // stays below 8 GiB
-        const int aocc_sa = adjoint_blocks_per_cu(c.aprec, c.E, c.r, true, grad);
-        const int64_t grid_sa = std::max<int64_t>(1, std::min<int64_t>((int64_t)aocc_sa * ncu, c.n_items));
-        const int64_t pool_sa = grid_sa * c.K * e3 * esz;
+        int64_t pool_sa = 0;
+        for (const Group &g : c.groups)
+            pool_sa = std::max<int64_t>(pool_sa, (int64_t)agrid(g, true) *
+                                                     storeall_slot_elems(c.K, g.E) * esz);
         c.storeall = params->ckpt_every == 1 ||
                      (params->ckpt_every == 0 && pool_sa <= (int64_t)8 << 30);
         // a store-all kernel without the column projector path (never the case
         // for the supported edges, but kept well defined) rebuilds with stride 10
         if (c.storeall) c.p.ckpt_every = 10;
-        const int aocc = adjoint_blocks_per_cu(c.aprec, c.E, c.r, c.storeall, grad);
-        c.grid_adj = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)aocc * ncu, c.n_items));
         c.n_ckpt = c.K >= 2 ? (c.K - 2) / c.p.ckpt_every + 1 : 1;
-        // a kernel without the column projector path falls back to the rebuild
-        // layout, so a store-all pool also covers that one
-        c.ckpt_stride = (int64_t)c.n_ckpt * 2 * e3;
-        if (c.storeall) c.ckpt_stride = std::max<int64_t>(c.ckpt_stride, (int64_t)c.K * e3);
-        const size_t n = (size_t)c.grid_adj * c.ckpt_stride;
+        c.ckpt_stride = 0;
+        int max_grid = 1;
+        for (Group &g : c.groups) {
+            g.grid_adj = agrid(g, c.storeall);
+            max_grid = std::max(max_grid, g.grid_adj);
+            const int64_t e3 = (int64_t)g.E * g.E * g.E;
+            // a kernel without the column projector path falls back to the
+            // rebuild layout, so a store-all slot also covers that one
+            int64_t st = (int64_t)c.n_ckpt * 2 * e3;
+            if (c.storeall) st = std::max<int64_t>(st, storeall_slot_elems(c.K, g.E));
+            c.ckpt_stride = std::max(c.ckpt_stride, st);
+        }
+        const size_t n = (size_t)max_grid * c.ckpt_stride;
         if (c.aprec == SQ_FP64) {
             double *q = nullptr;
             ALLOC(q, n);
@@ -591,6 +804,7 @@ sq_status sq_get_info(const sq_ctx *ctx, sq_info *info) {
     info->n_atoms = ctx->n_atoms;
     info->region_points = ctx->region_points;
     info->workspace_bytes = ctx->bytes;
+    info->n_launches = (int32_t)ctx->groups.size();
     return SQ_OK;
 }
 
@@ -631,54 +845,9 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
         HIP_TRY(k_set_bounds(c.d_scal, lambda_min, lambda_max, st));
     }
     HIP_TRY(k_build_diag(V, c.nv, c.kin, c.d_scal, c.d_D64, c.d_D32, st));
-    HIP_TRY(k_fill_i32(c.d_counter, 0, 1, st));
     HIP_TRY(k_fill_i32(c.d_status, 0, 1, st));
     double *mu = moments ? moments : c.d_mu;
-    if (c.prec == SQ_FP64) {
-        RegionArgs<double> a{};
-        a.items = c.d_items;
-        a.n_items = c.n_items;
-        a.counter = c.d_counter;
-        a.D = c.d_D64;
-        for (int x = 0; x < 3; ++x) { a.N[x] = c.N[x]; a.ih2[x] = c.ih2[x]; }
-        a.periodic = c.periodic;
-        a.scal = c.d_scal;
-        for (int p = 0; p <= MAX_R; ++p) a.w[p] = c.w[p];
-        a.h3 = c.h3;
-        a.K = c.K;
-        a.moments = mu;
-        a.n_atoms = c.n_atoms;
-        a.atoms = c.d_atoms;
-        a.sup_pack = c.d_pack;
-        a.colidx = c.d_colidx;
-        a.chi = c.d_chi64;
-        a.dchi = c.d_dchi64;
-        a.cJ = c.d_cJ;
-        a.status = c.d_status;
-        HIP_TRY(launch_forward(c.prec, c.E, c.r, c.maskz, &a, c.grid_fwd, st));
-    } else {
-        RegionArgs<float> a{};
-        a.items = c.d_items;
-        a.n_items = c.n_items;
-        a.counter = c.d_counter;
-        a.D = c.d_D32;
-        for (int x = 0; x < 3; ++x) { a.N[x] = c.N[x]; a.ih2[x] = c.ih2[x]; }
-        a.periodic = c.periodic;
-        a.scal = c.d_scal;
-        for (int p = 0; p <= MAX_R; ++p) a.w[p] = c.w[p];
-        a.h3 = c.h3;
-        a.K = c.K;
-        a.moments = mu;
-        a.n_atoms = c.n_atoms;
-        a.atoms = c.d_atoms;
-        a.sup_pack = c.d_pack;
-        a.colidx = c.d_colidx;
-        a.chi = c.d_chi32;
-        a.dchi = c.d_dchi32;
-        a.cJ = c.d_cJ;
-        a.status = c.d_status;
-        HIP_TRY(launch_forward(c.prec, c.E, c.r, c.maskz, &a, c.grid_fwd, st));
-    }
+    TRY(run_forward(c, c.groups, c.d_items, mu, st));
     HIP_TRY(k_moment_sum(mu, c.n_nodes, c.K, c.d_mpartial, c.n_mpart, c.d_M, moment_sum, st));
     c.mu_last = mu;
     c.have_density = true;
@@ -718,60 +887,33 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
     if (!dV && !dR) return SQ_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool grad = dR != nullptr;
-    HIP_TRY(k_fill_i32(c.d_counter, 0, 1, st));
-    auto fill = [&](auto &g) {
-        g.items = c.d_items;
-        g.n_items = c.n_items;
-        g.counter = c.d_counter;
-        for (int x = 0; x < 3; ++x) { g.N[x] = c.N[x]; g.ih2[x] = c.ih2[x]; }
-        g.periodic = c.periodic;
-        g.scal = c.d_scal;
-        for (int p = 0; p <= MAX_R; ++p) g.w[p] = c.w[p];
-        g.h3 = c.h3;
-        g.K = c.K;
-        g.moments = nullptr;
-        g.n_atoms = c.n_atoms;
-        g.atoms = c.d_atoms;
-        g.sup_pack = c.d_pack;
-        g.colidx = c.d_colidx;
-        g.cJ = c.d_cJ;
-        g.status = c.d_status;
+    HIP_TRY(k_fill_i32(c.d_counter, 0, (int64_t)c.groups.size(), st));
+    auto launch = [&](auto tag) -> sq_status {
+        using T = decltype(tag);
+        for (size_t g = 0; g < c.groups.size(); ++g) {
+            const Group &gr = c.groups[g];
+            AdjointArgs<T> a{};
+            fill_region_args(c, a.g);
+            a.g.items = c.d_items + gr.begin;
+            a.g.n_items = gr.count;
+            a.g.counter = c.d_counter + g;
+            a.g.moments = nullptr;
+            a.coef_c = c.fw.cp;
+            a.coef_d = c.fw.dp;
+            a.g_rho = g_rho;
+            a.g_u = g_u;
+            a.dV = dV;
+            a.dR = dR;
+            a.ckpt = static_cast<T *>(c.d_ckpt);
+            a.ckpt_every = c.p.ckpt_every;
+            a.n_ckpt = c.n_ckpt;
+            a.ckpt_stride = c.ckpt_stride;
+            HIP_TRY(launch_adjoint(c.aprec, gr.E, c.r, c.storeall, grad, &a, gr.grid_adj, st));
+        }
+        return SQ_OK;
     };
-    if (c.aprec == SQ_FP64) {
-        AdjointArgs<double> a{};
-        fill(a.g);
-        a.g.D = c.d_D64;
-        a.g.chi = c.d_chi64;
-        a.g.dchi = c.d_dchi64;
-        a.coef_c = c.fw.cp;
-        a.coef_d = c.fw.dp;
-        a.g_rho = g_rho;
-        a.g_u = g_u;
-        a.dV = dV;
-        a.dR = dR;
-        a.ckpt = static_cast<double *>(c.d_ckpt);
-        a.ckpt_every = c.p.ckpt_every;
-        a.n_ckpt = c.n_ckpt;
-        a.ckpt_stride = c.ckpt_stride;
-        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.storeall, grad, &a, c.grid_adj, st));
-    } else {
-        AdjointArgs<float> a{};
-        fill(a.g);
-        a.g.D = c.d_D32;
-        a.g.chi = c.d_chi32;
-        a.g.dchi = c.d_dchi32;
-        a.coef_c = c.fw.cp;
-        a.coef_d = c.fw.dp;
-        a.g_rho = g_rho;
-        a.g_u = g_u;
-        a.dV = dV;
-        a.dR = dR;
-        a.ckpt = static_cast<float *>(c.d_ckpt);
-        a.ckpt_every = c.p.ckpt_every;
-        a.n_ckpt = c.n_ckpt;
-        a.ckpt_stride = c.ckpt_stride;
-        HIP_TRY(launch_adjoint(c.aprec, c.E, c.r, c.storeall, grad, &a, c.grid_adj, st));
-    }
+    if (c.aprec == SQ_FP64) TRY(launch(double{}));
+    else TRY(launch(float{}));
     c.last_stream = st;
     return SQ_OK;
 }

@@ -31,7 +31,7 @@ constexpr int max_atoms_in_region() {
     constexpr int used = region_lds_elems<T, E>() * (int)sizeof(T) + 512 + FIXED;
     constexpr int per = (int)sizeof(Slot) + NP * (int)sizeof(T) + EXTRA;
     constexpr int n = (LDS_BYTES - used) / per;
-    return n > 128 ? 128 : (n < 0 ? 0 : n);
+    return n > MAX_REGION_ATOMS ? MAX_REGION_ATOMS : (n < 0 ? 0 : n);
 }
 
 // A block-uniform pointer pinned in scalar registers.  Per-z loads of a
@@ -263,6 +263,33 @@ __device__ __forceinline__ void projector_update(const RegionArgs<T> &a, const S
     }
 }
 
+// prev <- D cur - prev.  Without DREG the diagonal is re-read from L2 every
+// step: z is clamped into the box so the loads need no branch (entries past dz
+// are zeroed by the z mask, and boxes without one have dz = E), and an opaque
+// zero keeps the E uniform plane addresses from being hoisted out of the step
+// loop into spilled registers.
+template <typename T, int E, int R, bool DREG>
+__device__ __forceinline__ void diag_part(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                          const T (&d)[DREG ? E : 1], int64_t col,
+                                          int64_t plane, int gz0, int n2, const T (&cur)[E],
+                                          T (&prev)[E]) {
+    if constexpr (DREG) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
+    } else {
+        int salt = 0;
+        asm volatile("" : "+s"(salt));
+        const uint32_t cl = (uint32_t)col;
+        const int zmax = c.dz - 1 + salt;
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            int gz = gz0 + min(z, zmax);
+            gz = gz >= n2 ? gz - n2 : gz;
+            prev[z] = sgpr_ptr(a.D + plane * gz)[cl] * cur[z] - prev[z];
+        }
+    }
+}
+
 // One recurrence step in place: prev <- scale * (2 Hs cur) - prev.
 // (scale = 1/2 with prev = 0 gives v_1 = Hs v_0.)
 template <typename T, int E, int R, int ZS, int NW, bool MASKZ, bool DREG, bool GRAD = false>
@@ -280,19 +307,7 @@ __device__ __forceinline__ void region_step(const RegionArgs<T> &a, const StepCt
                                         c.dz, tau);
 
     // local part: D cur - prev, z neighbours from registers, x/y from LDS
-    if constexpr (DREG) {
-#pragma unroll
-        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
-    } else {
-        // D read back from L2 each step (its VGPRs are needed for the FP64 pencils)
-#pragma unroll
-        for (int z = 0; z < E; ++z) {
-            int gz = gz0 + z;
-            gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
-            prev[z] = dz * cur[z] - prev[z];
-        }
-    }
+    diag_part<T, E, R, DREG>(a, c, d, col, plane, gz0, n2, cur, prev);
 #pragma unroll
     for (int p = 1; p <= R; ++p) {
 #pragma unroll
@@ -368,10 +383,9 @@ __device__ __forceinline__ int build_columns(const RegionArgs<T> &a, const Slot 
 
 // raw projections of this thread's pencil (in LDS) onto the crossing supports,
 // reduced over the box with LDS atomics into the current parity buffer
-// (pencil z stride zs: 1 for the LDS copy, E^2 for a stored vector in HBM)
 template <typename T, bool GRAD>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
-                                         const T *pencil, int zs = 1) {
+                                         const T *pencil) {
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         T s[NP] = {0, 0, 0, 0};
@@ -380,8 +394,9 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
 #pragma unroll
             for (int i = 0; i < 3 * NP; ++i) g[i] = 0;
         }
+#pragma unroll 1
         for (int i = 0; i < e.n; ++i) {
-            const T v = pencil[(int64_t)(e.zlo + i) * zs];
+            const T v = pencil[e.zlo + i];
             const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
 #pragma unroll
             for (int l = 0; l < NP; ++l) s[l] += ch[l] * v;
@@ -413,6 +428,7 @@ __device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T
         T f[NP];
 #pragma unroll
         for (int l = 0; l < NP; ++l) f[l] = sc[l] * pa[l] * half;
+#pragma unroll 1
         for (int i = 0; i < e.n; ++i) {
             const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
             pencil[e.zlo + i] += ch[0] * f[0] + ch[1] * f[1] + ch[2] * f[2] + ch[3] * f[3];
@@ -437,18 +453,7 @@ __device__ __forceinline__ void local_part(const RegionArgs<T> &a, const StepCtx
                                            const T (&d)[DREG ? E : 1], int64_t col,
                                            int64_t plane, int gz0, int n2, const T (&cur)[E],
                                            T (&prev)[E], const T *lds) {
-    if constexpr (DREG) {
-#pragma unroll
-        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
-    } else {
-#pragma unroll
-        for (int z = 0; z < E; ++z) {
-            int gz = gz0 + z;
-            gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
-            prev[z] = dz * cur[z] - prev[z];
-        }
-    }
+    diag_part<T, E, R, DREG>(a, c, d, col, plane, gz0, n2, cur, prev);
 #pragma unroll
     for (int p = 1; p <= R; ++p) {
 #pragma unroll
@@ -478,18 +483,7 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
                                                   int64_t plane, int gz0, int n2,
                                                   const T (&cur)[E], T (&prev)[E],
                                                   const T *lds) {
-    if constexpr (DREG) {
-#pragma unroll
-        for (int z = 0; z < E; ++z) prev[z] = d[z] * cur[z] - prev[z];
-    } else {
-#pragma unroll
-        for (int z = 0; z < E; ++z) {
-            int gz = gz0 + z;
-            gz = gz >= n2 ? gz - n2 : gz;
-            const T dz = (c.active && z < c.dz) ? sgpr_ptr(a.D + plane * gz)[(uint32_t)col] : (T)0;
-            prev[z] = dz * cur[z] - prev[z];
-        }
-    }
+    diag_part<T, E, R, DREG>(a, c, d, col, plane, gz0, n2, cur, prev);
 #pragma unroll
     for (int p = 1; p <= R; ++p) {
 #pragma unroll
@@ -500,16 +494,22 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
             prev[z] += c.cz[p] * s;
         }
     }
-    const int tid = threadIdx.x;
-#pragma unroll 1
-    for (int q = 0; q < 4 * R; ++q) {
-        const int p = (q >> 2) + 1, dir = q & 3;
-        int nb;
-        if (dir == 0) nb = (c.active && c.px + p < c.dx) ? tid + p : c.npen;
-        else if (dir == 1) nb = (c.active && c.px - p >= 0) ? tid - p : c.npen;
-        else if (dir == 2) nb = (c.active && c.py + p < c.dy) ? tid + p * c.dx : c.npen;
-        else nb = (c.active && c.py - p >= 0) ? tid - p * c.dx : c.npen;
-        axpy_pencil<T, E, ZS>(prev, c.ncoef[q], lds + nb * ZS);
+    // neighbour offsets are recomputed per step from an opaque zero so the
+    // compiler does not keep 4R of them live across the step loop
+    int salt = 0;
+    asm volatile("" : "+v"(salt));
+    const int tid = threadIdx.x + salt;
+    const int px = c.px + salt, py = c.py + salt;
+#pragma unroll
+    for (int p = 1; p <= R; ++p) {
+        const int n0 = (c.active && px + p < c.dx) ? tid + p : c.npen;
+        axpy_pencil<T, E, ZS>(prev, c.cx[p], lds + n0 * ZS);
+        const int n1 = (c.active && px - p >= 0) ? tid - p : c.npen;
+        axpy_pencil<T, E, ZS>(prev, c.cx[p], lds + n1 * ZS);
+        const int n2_ = (c.active && py + p < c.dy) ? tid + p * c.dx : c.npen;
+        axpy_pencil<T, E, ZS>(prev, c.cy[p], lds + n2_ * ZS);
+        const int n3 = (c.active && py - p >= 0) ? tid - p * c.dx : c.npen;
+        axpy_pencil<T, E, ZS>(prev, c.cy[p], lds + n3 * ZS);
     }
 }
 
@@ -519,22 +519,15 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
 //      add the projector term to the own pencil, reload it.
 // cur is written to LDS at the start even when the previous step left the
 // same values there: a conditional store costs more registers than it saves.
-// With XDOTS the same window also projects a second vector xv (a stored v_k,
-// z stride xzs) into the state xnl, which then advances its parity too.
 template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
-          bool LOWREG = false, bool XDOTS = false>
+          bool LOWREG = false>
 __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
                                                 const T (&d)[DREG ? E : 1], int64_t col,
                                                 int64_t plane, int gz0, int n2, T (&cur)[E],
-                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first,
-                                                ColNL<T> *xnl = nullptr, const T *xv = nullptr,
-                                                int xzs = 1) {
+                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
-    if constexpr (XDOTS) {
-        if (xnl->ncol) col_dots<T, GRAD>(a, *xnl, xv, xzs);
-    }
     if constexpr (LOWREG)
         local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
     else
@@ -553,31 +546,20 @@ __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const St
         if (nl.ncol) col_update<T>(a, nl, c.mine, first ? (T)0.5 : (T)1);
         if (c.active) load_pencil<T, E, ZS>(c.mine, prev);
         col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
-        if constexpr (XDOTS) col_zero_next<T, BLOCK, GRAD>(*xnl, c.nat);
     }
     nl.par ^= 1;
-    if constexpr (XDOTS) xnl->par ^= 1;
 }
 
 // projections of one vector without a recurrence step (column path)
-template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD, bool XDOTS = false>
+template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD>
 __device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
-                                              const T (&vec)[E], ColNL<T> &nl,
-                                              ColNL<T> *xnl = nullptr, const T *xv = nullptr,
-                                              int xzs = 1) {
+                                              const T (&vec)[E], ColNL<T> &nl) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
-    if constexpr (XDOTS) {
-        if (xnl->ncol) col_dots<T, GRAD>(a, *xnl, xv, xzs);
-    }
     __syncthreads();
     col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
     nl.par ^= 1;
-    if constexpr (XDOTS) {
-        col_zero_next<T, BLOCK, GRAD>(*xnl, c.nat);
-        xnl->par ^= 1;
-    }
 }
 
 template <typename T, int E>

@@ -34,7 +34,8 @@ class Context:
     """A spectral-quadrature context for one problem geometry (sq_setup)."""
 
     def __init__(self, prob: Problem, precision: Optional[int] = None, nodes=None,
-                 node_rcut=None, ckpt_every: int = 0, adjoint_precision: int = L.SQ_FP64):
+                 node_rcut=None, ckpt_every: int = 0, adjoint_precision: int = L.SQ_FP64,
+                 tune: int = 0):
         p = L.sq_params()
         p.n[:] = [int(x) for x in prob.n]
         p.h[:] = [float(x) for x in prob.h]
@@ -46,6 +47,7 @@ class Context:
         p.precision = int(prob.precision if precision is None else precision)
         p.ckpt_every = int(ckpt_every)
         p.adjoint_precision = int(adjoint_precision)
+        p.tune = int(tune)
         self.params = p
         self.prob = prob
         self._keep = []

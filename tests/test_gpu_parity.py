@@ -35,9 +35,11 @@ def rel_err(a, b):
 
 
 def gpu_forward(prob, lmin, lmax, precision, nodes=None, node_rcut=None, Ne=None, lf=None,
-                tol=1e-10):
+                tol=1e-10, tune=0, info=None):
     sq = _sq()
-    ctx = sq.Context(prob, precision=precision, nodes=nodes, node_rcut=node_rcut)
+    ctx = sq.Context(prob, precision=precision, nodes=nodes, node_rcut=node_rcut, tune=tune)
+    if info is not None:
+        info.append(ctx.info)
     V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
     mu, M = ctx.density(V, lmin, lmax)
     if Ne is not None:
@@ -149,13 +151,21 @@ def test_config2_sampled(precision):
     assert abs(g["tot"][0] - prob.Ne) < 1e-8 * prob.Ne
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_config3_uneven_clipped(precision):
-    """4096 uneven Dirichlet-clipped regions in one persistent launch."""
-    print(f"[case] config3 precision={precision}", flush=True)
+@pytest.mark.parametrize("precision,tune", [(0, 0), (1, 0), (1, 1)])
+def test_config3_uneven_clipped(precision, tune):
+    """4096 uneven Dirichlet-clipped regions (edges 11..27 before clipping):
+    the launch plan the tuner picks (tune 0), and one persistent launch per
+    edge bucket (tune 1)."""
+    print(f"[case] config3 precision={precision} tune={tune}", flush=True)
     prob = synth.config(3)
     lmin, lmax = O.lanczos_bounds(prob, steps=60)
-    g = gpu_forward(prob, lmin, lmax, precision, lf=prob.lambda_f)
+    info = []
+    g = gpu_forward(prob, lmin, lmax, precision, lf=prob.lambda_f, tune=tune, info=info)
+    print(f"persistent launches per pass: {info[0].n_launches}")
+    if tune == 1:
+        assert info[0].n_launches > 1
+    else:
+        assert info[0].n_launches >= 1
     nodes, widths = prob.nodes, prob.node_rcut
     # sample: the smallest and largest boxes, clipped and interior ones
     sizes = []
@@ -228,3 +238,58 @@ def test_edge_cases_single_node_and_thin_boxes():
             ref = O.moments(prob, lmin, lmax, nodes=nodes)
             tol = 1e-13 if precision == 0 else 1e-6
             assert np.abs(g["mu"] - ref).max() < tol
+
+
+def test_config5_embedded_full_fp32_sampled():
+    """Embedded 128^3 domain (V and projectors on the 154^3 padded grid, 1791
+    projector atoms, K = 120): all 2,097,152 nodes in one FP32 launch with the
+    FP64 bisection on N_e = 1534; sampled nodes (corners of Omega, whose
+    regions reach into the padding, and random interior nodes) against the
+    oracle.  Gershgorin bounds from the oracle are passed to both sides."""
+    print("[case] config5 embedded FP32 full", flush=True)
+    sq = _sq()
+    prob = synth.config(5)
+    lmin, lmax = O.gershgorin(prob)
+    n0, n1, n2 = prob.n
+    corners = [i + n0 * (j + n1 * k) for i in (0, n0 - 1) for j in (0, n1 - 1)
+               for k in (0, n2 - 1)]
+    rng = np.random.default_rng(55)
+    sample = np.unique(np.concatenate([corners, rng.choice(prob.n_nodes, 10, replace=False)]))
+    ctx = sq.Context(prob, precision=1)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    mu, M = ctx.density(V, lmin, lmax)
+    lam, rho, u, tot = ctx.fermi_level(Ne=prob.Ne, tol=1e-8, max_iter=200)
+    torch.cuda.synchronize()
+    ctx.status()
+    idx = torch.tensor(sample, device="cuda")
+    mu_s = mu[idx].cpu().numpy()
+    rho_all = rho.cpu().numpy()
+    tot = tot.cpu().numpy()
+    lf = float(lam.item())
+    ctx.close()
+    mu_ref = O.moments(prob, lmin, lmax, nodes=sample)
+    assert np.abs(mu_s - mu_ref).max() < fp32_mu_tol(prob.order)
+    rho_ref, _ = oracle_fields(mu_ref, lf, prob.kT, lmin, lmax, prob.order)
+    assert np.abs(rho_all[sample] - rho_ref).max() / np.abs(rho_all).max() < 1e-5
+    assert abs(tot[0] - prob.Ne) < 1e-8 * prob.Ne
+    assert abs(rho_all.sum() - prob.Ne) < 1e-6 * prob.Ne
+
+
+def test_config5_embedded_fp64_nodes():
+    """Embedded workload, FP64 path on a node subset (including the corners of
+    Omega) against the oracle at the FP64 tolerances."""
+    print("[case] config5 embedded FP64 subset", flush=True)
+    prob = synth.config(5)
+    lmin, lmax = O.gershgorin(prob)
+    n0, n1, n2 = prob.n
+    corners = [i + n0 * (j + n1 * k) for i in (0, n0 - 1) for j in (0, n1 - 1)
+               for k in (0, n2 - 1)]
+    rng = np.random.default_rng(56)
+    nodes = np.unique(np.concatenate([corners, rng.choice(prob.n_nodes, 24, replace=False)]))
+    lf = 0.5 * (lmin + lmax) - 0.45 * (lmax - lmin)
+    g = gpu_forward(prob, lmin, lmax, 0, nodes=nodes, lf=lf)
+    mu_ref = O.moments(prob, lmin, lmax, nodes=nodes)
+    assert np.abs(g["mu"] - mu_ref).max() < 1e-12
+    rho_ref, u_ref = oracle_fields(mu_ref, lf, prob.kT, lmin, lmax, prob.order)
+    assert rel_err(g["rho"], rho_ref) < 1e-10
+    assert rel_err(g["u"], u_ref) < 1e-10
