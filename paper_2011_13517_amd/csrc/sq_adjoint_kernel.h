@@ -226,14 +226,26 @@ __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
                         g[i] = sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t];
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < CH; ++i)
                     if (z0 + i < E) sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t] = g[i] + alpha * ta[z0 + i] * vk[i];
             }
         } else {
+            // all loads first, then the FMAs: one memory wait instead of one
+            // per z (left alone, the allocator serialises the loads)
+            constexpr int CH = E;
 #pragma unroll
-            for (int z = 0; z < E; ++z)
-                G[z] += alpha * ta[z] * sgpr_ptr(ck + ((int64_t)k * E + z) * EE)[t];
+            for (int z0 = 0; z0 < E; z0 += CH) {
+                T vk[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (z0 + i < E) vk[i] = sgpr_ptr(ck + ((int64_t)k * E + z0 + i) * EE)[t];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (z0 + i < E) G[z0 + i] += alpha * ta[z0 + i] * vk[i];
+            }
         }
     }
     if (k >= 1) {
@@ -447,20 +459,22 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             // slot layout [k][z][pencil]: a wave's stores coalesce
             // (v_K itself is never needed by the reverse sweep).  With GRAD the
             // step's projections of v_k (chi and dchi/dR) go to the slot too.
+            // A step that advances v_k also stores v_k (its input) inside the
+            // step; the last vector v_{K-1} is stored after the loop.
             constexpr int E3 = E * E * E;
-            ck_store<T, E>(ck, c.active, tid, 0, 0, v);
             for (int k = 0; k + 1 <= K - 1; k += 2) {
                 region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
-                    a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0);
-                ck_store<T, E>(ck, c.active, tid, 0, k + 1, w);
+                    a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0, ck + (int64_t)k * E3);
                 if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k);
                 if (k + 2 <= K - 1) {
                     region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
-                        a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false);
-                    ck_store<T, E>(ck, c.active, tid, 0, k + 2, v);
+                        a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false,
+                        ck + (int64_t)(k + 1) * E3);
                     if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k + 1);
                 }
             }
+            if ((K - 1) % 2 == 0) ck_store<T, E>(ck, c.active, tid, 0, K - 1, v);
+            else ck_store<T, E>(ck, c.active, tid, 0, K - 1, w);
             if constexpr (GRAD) {
                 // projections of v_{K-1}, the last stored vector
                 if ((K - 1) % 2 == 0) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, v, nlB);

@@ -281,11 +281,24 @@ __device__ __forceinline__ void diag_part(const RegionArgs<T> &a, const StepCtx<
         asm volatile("" : "+s"(salt));
         const uint32_t cl = (uint32_t)col;
         const int zmax = c.dz - 1 + salt;
+        // all loads first, then the FMAs: one memory wait per step (left
+        // alone, the allocator issues load, wait, FMA per z)
+        constexpr int CH = E;
 #pragma unroll
-        for (int z = 0; z < E; ++z) {
-            int gz = gz0 + min(z, zmax);
-            gz = gz >= n2 ? gz - n2 : gz;
-            prev[z] = sgpr_ptr(a.D + plane * gz)[cl] * cur[z] - prev[z];
+        for (int z0 = 0; z0 < E; z0 += CH) {
+            T dv[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                if (z0 + i < E) {
+                    int gz = gz0 + min(z0 + i, zmax);
+                    gz = gz >= n2 ? gz - n2 : gz;
+                    dv[i] = sgpr_ptr(a.D + plane * gz)[cl];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (z0 + i < E) prev[z0 + i] = dv[i] * cur[z0 + i] - prev[z0 + i];
         }
     }
 }
@@ -476,13 +489,17 @@ __device__ __forceinline__ void local_part(const RegionArgs<T> &a, const StepCtx
 // Same as local_part with a runtime loop over the 4R neighbour pencils, for
 // kernels that keep more pencils resident (the adjoint): one neighbour pencil
 // is in flight at a time instead of all 4R.
+// With st non-null, cur is also stored to st ([z][pencil], E^2 apart) right
+// after its last register use: the stores then overlap the LDS half of the
+// step instead of delaying the next step's loads (which share the vector
+// memory counter with them).
 template <typename T, int E, int R, int ZS, bool DREG>
 __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
                                                   const StepCtx<T, E, R> &c,
                                                   const T (&d)[DREG ? E : 1], int64_t col,
                                                   int64_t plane, int gz0, int n2,
                                                   const T (&cur)[E], T (&prev)[E],
-                                                  const T *lds) {
+                                                  const T *lds, T *st) {
     diag_part<T, E, R, DREG>(a, c, d, col, plane, gz0, n2, cur, prev);
 #pragma unroll
     for (int p = 1; p <= R; ++p) {
@@ -493,6 +510,10 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
             if (z - p >= 0) s += cur[z - p];
             prev[z] += c.cz[p] * s;
         }
+    }
+    if (st && c.active) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) sgpr_ptr(st + (int64_t)z * E * E)[threadIdx.x] = cur[z];
     }
     // neighbour offsets are recomputed per step from an opaque zero so the
     // compiler does not keep 4R of them live across the step loop
@@ -519,17 +540,19 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
 //      add the projector term to the own pencil, reload it.
 // cur is written to LDS at the start even when the previous step left the
 // same values there: a conditional store costs more registers than it saves.
+// (st: see local_part_lowreg; LOWREG steps only)
 template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
           bool LOWREG = false>
 __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
                                                 const T (&d)[DREG ? E : 1], int64_t col,
                                                 int64_t plane, int gz0, int n2, T (&cur)[E],
-                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first) {
+                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first,
+                                                T *st = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
     if constexpr (LOWREG)
-        local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
+        local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds, st);
     else
         local_part<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
     __syncthreads();
