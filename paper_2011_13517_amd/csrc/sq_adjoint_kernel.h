@@ -215,7 +215,7 @@ __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
     if (c.active) {
         const uint32_t t = threadIdx.x;
         if constexpr (GHBM) {
-            constexpr int CH = 9;
+            constexpr int CH = E;
 #pragma unroll
             for (int z0 = 0; z0 < E; z0 += CH) {
                 T vk[CH], g[CH];
@@ -265,15 +265,23 @@ __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
         const T *gA = nlA.gacc + (int64_t)(nlA.par ^ 1) * nlA.maxat * 3 * NP;
         const T *pk = ck + (int64_t)a.K * E * EE + (int64_t)k * MAX_REGION_ATOMS * 4 * NP;
         for (int j = threadIdx.x; j < c.nat; j += BLOCK) {
-            const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+            // all loads of the atom first (one memory wait), then the sums
+            const double *cjp = a.cJ + (int64_t)slots[j].atom * NP;
             const T *pj = pk + j * 4 * NP;
+            double cj[NP];
+            T pv[4 * NP];
+#pragma unroll
+            for (int l = 0; l < NP; ++l) cj[l] = cjp[l];
+#pragma unroll
+            for (int q = 0; q < 4 * NP; ++q) pv[q] = pj[q];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
                 double s = 0.0;
 #pragma unroll
                 for (int l = 0; l < NP; ++l)
-                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)pj[l] +
-                                  (double)dA[j * NP + l] * (double)pj[NP + l * 3 + x]);
+                    s += cj[l] * ((double)gA[(j * NP + l) * 3 + x] * (double)pv[l] +
+                                  (double)dA[j * NP + l] * (double)pv[NP + l * 3 + x]);
                 dRacc[j][x] += f * s;
             }
         }

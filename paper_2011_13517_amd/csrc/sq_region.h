@@ -396,9 +396,12 @@ __device__ __forceinline__ int build_columns(const RegionArgs<T> &a, const Slot 
 
 // raw projections of this thread's pencil (in LDS) onto the crossing supports,
 // reduced over the box with LDS atomics into the current parity buffer
+// The support rows of a column piece are read in batches of NB (loads of the
+// batch first, then its FMAs), so one L2 round trip serves NB rows.
 template <typename T, bool GRAD>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
                                          const T *pencil) {
+    constexpr int NB = GRAD ? 2 : 4;
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         T s[NP] = {0, 0, 0, 0};
@@ -407,16 +410,30 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
 #pragma unroll
             for (int i = 0; i < 3 * NP; ++i) g[i] = 0;
         }
-#pragma unroll 1
-        for (int i = 0; i < e.n; ++i) {
-            const T v = pencil[e.zlo + i];
-            const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            T ch[NB][NP], dc[GRAD ? NB : 1][GRAD ? 3 * NP : 1], v[NB];
 #pragma unroll
-            for (int l = 0; l < NP; ++l) s[l] += ch[l] * v;
-            if constexpr (GRAD) {
-                const T *dc = a.dchi + (int64_t)(e.row0 + i) * 3 * NP;
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);   // a short batch re-reads its last row
+                const T *chp = a.chi + (int64_t)(e.row0 + i) * NP;
 #pragma unroll
-                for (int q = 0; q < 3 * NP; ++q) g[q] += dc[q] * v;
+                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
+                if constexpr (GRAD) {
+                    const T *dcp = a.dchi + (int64_t)(e.row0 + i) * 3 * NP;
+#pragma unroll
+                    for (int q = 0; q < 3 * NP; ++q) dc[b][q] = dcp[q];
+                }
+                v[b] = i0 + b < e.n ? pencil[e.zlo + i] : (T)0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                for (int l = 0; l < NP; ++l) s[l] += ch[b][l] * v[b];
+                if constexpr (GRAD) {
+#pragma unroll
+                    for (int q = 0; q < 3 * NP; ++q) g[q] += dc[b][q] * v[b];
+                }
             }
         }
         T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
@@ -434,6 +451,7 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
 template <typename T>
 __device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T> &nl, T *pencil,
                                            T half) {
+    constexpr int NB = 4;
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         const T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
@@ -441,10 +459,21 @@ __device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T
         T f[NP];
 #pragma unroll
         for (int l = 0; l < NP; ++l) f[l] = sc[l] * pa[l] * half;
-#pragma unroll 1
-        for (int i = 0; i < e.n; ++i) {
-            const T *ch = a.chi + (int64_t)(e.row0 + i) * NP;
-            pencil[e.zlo + i] += ch[0] * f[0] + ch[1] * f[1] + ch[2] * f[2] + ch[3] * f[3];
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            T ch[NB][NP];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);
+                const T *chp = a.chi + (int64_t)(e.row0 + i) * NP;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (i0 + b < e.n)
+                    pencil[e.zlo + i0 + b] +=
+                        ch[b][0] * f[0] + ch[b][1] * f[1] + ch[b][2] * f[2] + ch[b][3] * f[3];
         }
     }
 }
