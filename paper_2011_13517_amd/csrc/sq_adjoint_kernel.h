@@ -195,23 +195,14 @@ __device__ __forceinline__ void adjoint_rstep_col(const AdjointArgs<T> &aa,
     }
 }
 
-// Reverse step when the forward pass stored every v_k (checkpoint stride 1):
-// G += alpha vt_{k+1} v_k and tb <- vt_k.  v_k is read from its HBM slot where
-// it is used (the G update) instead of being held as a register pencil, so only
-// vt_{k+1}, vt_{k+2} and G stay resident; the projections of v_k needed for dR
-// were stored by the forward sweep next to the vectors.
-// With GHBM the accumulator G lives in the slot (gb, [z][pencil], L2-resident)
-// and is updated in chunks of loads then stores, instead of in registers.
-template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD, bool GHBM>
-__device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
-                                                 const StepCtx<T, E, R> &c, const AdjNode &nd,
-                                                 const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
-                                                 const Slot *slots, double (*dRacc)[3],
-                                                 const T *ck, T *gb, int k, T (&ta)[E],
-                                                 T (&tb)[E], T (&G)[GHBM ? 1 : E], double tau) {
-    const RegionArgs<T> &a = aa.g;
+// G += alpha vt_{k+1} v_k with v_k read from its stored slot.  All loads are
+// issued before the FMAs (one memory wait; left alone, the allocator issues
+// load, wait, FMA per z).  With GHBM the accumulator is the slot's
+// [z][pencil] array gb (L2-resident) instead of registers.
+template <typename T, int E, bool GHBM, typename Ctx>
+__device__ __forceinline__ void sa_gupdate(const Ctx &c, const T *ck, T *gb, int k, T alpha,
+                                           const T (&ta)[E], T (&G)[GHBM ? 1 : E]) {
     constexpr int EE = E * E;
-    const T alpha = k == 0 ? (T)1 : (T)2;
     if (c.active) {
         const uint32_t t = threadIdx.x;
         if constexpr (GHBM) {
@@ -248,6 +239,26 @@ __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
             }
         }
     }
+}
+
+// Reverse step when the forward pass stored every v_k (checkpoint stride 1):
+// G += alpha vt_{k+1} v_k and tb <- vt_k.  v_k is read from its HBM slot where
+// it is used (the G update) instead of being held as a register pencil, so only
+// vt_{k+1}, vt_{k+2} and G stay resident; the projections of v_k needed for dR
+// were stored by the forward sweep next to the vectors.
+// With GHBM the accumulator G lives in the slot (gb, [z][pencil], L2-resident)
+// and is updated in chunks of loads then stores, instead of in registers.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD, bool GHBM>
+__device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
+                                                 const StepCtx<T, E, R> &c, const AdjNode &nd,
+                                                 const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
+                                                 const Slot *slots, double (*dRacc)[3],
+                                                 const T *ck, T *gb, int k, T (&ta)[E],
+                                                 T (&tb)[E], T (&G)[GHBM ? 1 : E], double tau) {
+    const RegionArgs<T> &a = aa.g;
+    constexpr int EE = E * E;
+    const T alpha = k == 0 ? (T)1 : (T)2;
+    sa_gupdate<T, E, GHBM>(c, ck, gb, k, alpha, ta, G);
     if (k >= 1) {
         region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
             a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false);
@@ -290,15 +301,99 @@ __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
 
 // copy the projections of the vector the last step projected (parity buffer
 // par ^ 1 of nl) into the store-all slot, row k
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool WITHG = true>
 __device__ __forceinline__ void store_projections(const ColNL<T> &nl, int nat, T *ck, int K,
                                                   int E3, int k) {
     T *pk = ck + (int64_t)K * E3 + (int64_t)k * MAX_REGION_ATOMS * 4 * NP;
     const T *pa = nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP;
-    const T *ga = nl.gacc + (int64_t)(nl.par ^ 1) * nl.maxat * 3 * NP;
-    for (int i = threadIdx.x; i < nat * 4 * NP; i += BLOCK) {
-        const int j = i / (4 * NP), q = i - j * 4 * NP;
-        pk[i] = q < NP ? pa[j * NP + q] : ga[j * 3 * NP + (q - NP)];
+    if constexpr (WITHG) {
+        const T *ga = nl.gacc + (int64_t)(nl.par ^ 1) * nl.maxat * 3 * NP;
+        for (int i = threadIdx.x; i < nat * 4 * NP; i += BLOCK) {
+            const int j = i / (4 * NP), q = i - j * 4 * NP;
+            pk[i] = q < NP ? pa[j * NP + q] : ga[j * 3 * NP + (q - NP)];
+        }
+    } else {
+        for (int i = threadIdx.x; i < nat * NP; i += BLOCK) {
+            const int j = i / NP, q = i - j * NP;
+            pk[j * 4 * NP + q] = pa[i];
+        }
+    }
+}
+
+// dR in W mode (store-all adjoint).  With p_k = chi . v_k (stored by the
+// forward sweep) and q_k = chi . vt_{k+1} (the reverse step's projections),
+// the dR sum over k of alpha_k [(vt_{k+1} . dchi)(chi . v_k) +
+// (vt_{k+1} . chi)(dchi . v_k)] equals dchi . W with
+// W(y) = sum_k alpha_k (p_k vt_{k+1}(y) + q_k v_k(y)) on the support rows.  W is
+// accumulated per row of the thread's column pieces (in the slot,
+// [column][row][l][thread]) inside the reverse steps, and contracted with
+// dchi once per region, so no dchi projections are formed per step.
+// contraction of W with dchi/dR into the per-atom accumulators of the box
+template <typename T, int E, int BLOCK>
+__device__ __forceinline__ void w_contract(const RegionArgs<T> &a, const ColNL<T> &nl,
+                                           const Slot *slots, const T *wb, double (*cdR)[3],
+                                           double scale) {
+    constexpr int NB = 2;
+    const uint32_t t = threadIdx.x;
+    for (int cc = 0; cc < nl.ncol; ++cc) {
+        const ColEntry e = nl.cols[cc];
+        double cj[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) cj[l] = a.cJ[(int64_t)slots[e.slot].atom * NP + l];
+        const T *wc = wb + (int64_t)cc * E * NP * BLOCK + t;
+        double sx[3] = {0.0, 0.0, 0.0};
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            T dc[NB][3 * NP], wv[NB][NP];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);
+                const T *dcp = a.dchi + (int64_t)(e.row0 + i) * 3 * NP;
+#pragma unroll
+                for (int q = 0; q < 3 * NP; ++q) dc[b][q] = dcp[q];
+#pragma unroll
+                for (int l = 0; l < NP; ++l) wv[b][l] = i0 + b < e.n ? wc[((int64_t)i * NP + l) * BLOCK] : (T)0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int l = 0; l < NP; ++l)
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+                        sx[x] += cj[l] * (double)dc[b][l * 3 + x] * (double)wv[b][l];
+        }
+#pragma unroll
+        for (int x = 0; x < 3; ++x) atomicAdd(&cdR[e.slot][x], sx[x] * scale);
+    }
+}
+
+// Reverse step of the store-all adjoint with dR in W mode.  Reverse step k
+// (own pencil vt_{k+1} after its first barrier, the projection buffer of step
+// k+1 still holding q_{k+1}) adds alpha_k p_k vt_{k+1} + alpha_{k+1} q_{k+1} v_{k+1};
+// the last term alpha_0 q_0 v_0 is added after the k = 0 projections.
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GHBM>
+__device__ __forceinline__ void adjoint_rstep_saw(const AdjointArgs<T> &aa,
+                                                  const StepCtx<T, E, R> &c, const AdjNode &nd,
+                                                  const T (&d)[DREG ? E : 1], T *lds,
+                                                  ColNL<T> &nlA, const T *ck, T *gb, T *wb, int k,
+                                                  T (&ta)[E], T (&tb)[E], T (&G)[GHBM ? 1 : E]) {
+    const RegionArgs<T> &a = aa.g;
+    const T alpha = k == 0 ? (T)1 : (T)2;
+    sa_gupdate<T, E, GHBM>(c, ck, gb, k, alpha, ta, G);
+    WArgs<T> w{ck, wb, k, alpha, k + 1 <= a.K - 1 ? k + 1 : -1, (T)2, nlA.par ^ 1};
+    if (k >= 1) {
+        region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true, true>(
+            a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false, nullptr, &w);
+        if (nd.is_ctr) {
+            const T ak = (T)(2.0 * (nd.gr * aa.coef_c[k] + nd.gu * aa.coef_d[k]));
+#pragma unroll
+            for (int z = 0; z < E; ++z) tb[z] += (z == nd.cz0) ? ak : (T)0;
+        }
+    } else {
+        col_dots_only<T, E, R, ZS, BLOCK, false, true>(a, c, ta, nlA, &w);
+        // alpha_0 q_0 v_0 (q_0 now in buffer par ^ 1; own pencil unused: ap = 0)
+        WArgs<T> w0{ck, wb, 0, (T)0, 0, (T)1, nlA.par ^ 1};
+        if (nlA.ncol) w_update<T, E, BLOCK>(a, nlA, w0, c.mine);
     }
 }
 
@@ -309,16 +404,20 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
     constexpr int ZS = pencil_stride<T, E>();
     constexpr int NW = BLOCK / 64;
     constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
-    // column path: two projection states (vt and v), each [2][AT][NP] (+ [2][AT][3NP])
-    constexpr int CEXTRA = (GRAD ? 16 * NP : 4 * NP) * (int)sizeof(T) + (GRAD ? 24 : 0);
+    // column path: two projection states (vt and v), each [2][AT][NP] (+ [2][AT][3NP]
+    // with dR, except in the store-all W mode), and the dR accumulators
+    constexpr int CEXTRA = !GRAD ? 4 * NP * (int)sizeof(T)
+                                 : (STOREALL ? 4 * NP * (int)sizeof(T) + 24
+                                             : 16 * NP * (int)sizeof(T) + 24);
     constexpr bool COLNL = max_atoms_in_region<T, E, CEXTRA, COLBYTES>() >= 32;
+    constexpr bool WM = COLNL && STOREALL && GRAD;
     constexpr int EXTRA = GRAD ? (8 * NP * (int)sizeof(T) + 24) : 0;
     constexpr int MAXAT = COLNL ? max_atoms_in_region<T, E, CEXTRA, COLBYTES>()
                                 : max_atoms_in_region<T, E, EXTRA>();
     constexpr int AT = MAXAT > 0 ? MAXAT : 1;
     constexpr int GA = (GRAD && !COLNL) ? AT : 1;
     constexpr int CA = COLNL ? AT : 1;
-    constexpr int CG = (COLNL && GRAD) ? AT : 1;
+    constexpr int CG = (COLNL && GRAD && !WM) ? AT : 1;
     constexpr bool DREG = sizeof(T) == 4 ? E <= 21 : E <= 13;
     // store-all kernels with dR whose pencils do not fit the registers keep the
     // dV accumulator in their slot instead
@@ -433,8 +532,10 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                     cpA[0][j][l] = cpA[1][j][l] = cpB[0][j][l] = cpB[1][j][l] = (T)0;
                 }
                 if constexpr (GRAD) {
-                    for (int q = 0; q < 3 * NP; ++q)
-                        cgA[0][j][q] = cgA[1][j][q] = cgB[0][j][q] = cgB[1][j][q] = (T)0;
+                    if constexpr (!WM) {
+                        for (int q = 0; q < 3 * NP; ++q)
+                            cgA[0][j][q] = cgA[1][j][q] = cgB[0][j][q] = cgB[1][j][q] = (T)0;
+                    }
                     cdR[j][0] = cdR[j][1] = cdR[j][2] = 0.0;
                 }
             }
@@ -449,13 +550,14 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             nlA.maxat = nlB.maxat = CA;
             nlA.pacc = &cpA[0][0][0];
             nlB.pacc = &cpB[0][0][0];
-            nlA.gacc = GRAD ? &cgA[0][0][0] : nullptr;
-            nlB.gacc = GRAD ? &cgB[0][0][0] : nullptr;
+            nlA.gacc = (GRAD && !WM) ? &cgA[0][0][0] : nullptr;
+            nlB.gacc = (GRAD && !WM) ? &cgB[0][0][0] : nullptr;
             __syncthreads();
         }
 
         T v[E], G[GHBM ? 1 : E];
-        T *gb = ck + storeall_slot_elems(K, E) - (int64_t)E * E * E;
+        T *gb = ck + (int64_t)K * E * E * E + storeall_proj_elems(K);
+        T *wb = gb + (int64_t)E * E * E;
         if constexpr (COLNL && STOREALL) {
             // ---- forward storing v_0 .. v_{K-1}; reverse reads them back ----
             T w[E];
@@ -470,24 +572,36 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             // A step that advances v_k also stores v_k (its input) inside the
             // step; the last vector v_{K-1} is stored after the loop.
             constexpr int E3 = E * E * E;
+            // In W mode (dR) only the value projections chi . v_k are kept.
+            constexpr bool FG = GRAD && !WM;
             for (int k = 0; k + 1 <= K - 1; k += 2) {
-                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, FG, true>(
                     a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0, ck + (int64_t)k * E3);
-                if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k);
+                if constexpr (GRAD) store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, k);
                 if (k + 2 <= K - 1) {
-                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, FG, true>(
                         a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false,
                         ck + (int64_t)(k + 1) * E3);
-                    if constexpr (GRAD) store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, k + 1);
+                    if constexpr (GRAD) store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, k + 1);
                 }
             }
             if ((K - 1) % 2 == 0) ck_store<T, E>(ck, c.active, tid, 0, K - 1, v);
             else ck_store<T, E>(ck, c.active, tid, 0, K - 1, w);
             if constexpr (GRAD) {
                 // projections of v_{K-1}, the last stored vector
-                if ((K - 1) % 2 == 0) col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, v, nlB);
-                else col_dots_only<T, E, R, ZS, BLOCK, GRAD>(a, c, w, nlB);
-                store_projections<T, BLOCK>(nlB, c.nat, ck, K, E3, K - 1);
+                if ((K - 1) % 2 == 0) col_dots_only<T, E, R, ZS, BLOCK, FG>(a, c, v, nlB);
+                else col_dots_only<T, E, R, ZS, BLOCK, FG>(a, c, w, nlB);
+                store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, K - 1);
+            }
+            if constexpr (WM) {
+                // zero the W rows of this thread's column pieces
+                for (int cc = 0; cc < nlA.ncol; ++cc) {
+                    const ColEntry e = nlA.cols[cc];
+                    for (int i = 0; i < e.n; ++i)
+#pragma unroll
+                        for (int l = 0; l < NP; ++l)
+                            wb[(((int64_t)cc * E + i) * NP + l) * BLOCK + tid] = (T)0;
+                }
             }
             T t1[E], t2[E];
             const T aK = (T)(2.0 * (nd.gr * aa.coef_c[K] + nd.gu * aa.coef_d[K]));
@@ -501,12 +615,23 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                     G[z] = (T)0;
                 }
             }
-            for (int k = K - 1; k >= 0; k -= 2) {
-                adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
-                    aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k, t1, t2, G, tau);
-                if (k - 1 >= 0)
+            if constexpr (WM) {
+                for (int k = K - 1; k >= 0; k -= 2) {
+                    adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG, GHBM>(
+                        aa, c, nd, d, lds, nlA, ck, gb, wb, k, t1, t2, G);
+                    if (k - 1 >= 0)
+                        adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG, GHBM>(
+                            aa, c, nd, d, lds, nlA, ck, gb, wb, k - 1, t2, t1, G);
+                }
+                w_contract<T, E, BLOCK>(a, nlA, slots, wb, cdR, a.h3 / tau);
+            } else {
+                for (int k = K - 1; k >= 0; k -= 2) {
                     adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
-                        aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k - 1, t2, t1, G, tau);
+                        aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k, t1, t2, G, tau);
+                    if (k - 1 >= 0)
+                        adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
+                            aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k - 1, t2, t1, G, tau);
+                }
             }
         } else {
             // ---- forward: v_0 .. v_K, checkpoints (v_cC, v_cC+1) for cC+1 <= K-1 ----

@@ -18,8 +18,14 @@ constexpr int MAX_REGION_ATOMS = 128;  // cap on the atom list of one region box
 // the dV accumulator of the box ([z][pencil]) for kernels that keep it in
 // memory rather than in registers
 constexpr int64_t storeall_proj_elems(int K) { return (int64_t)K * MAX_REGION_ATOMS * 4 * NP; }
+constexpr int MAXC = 4;    // atom supports crossing one pencil of a box
+// dR accumulators W of the store-all adjoint: [column][row in the piece][NP][thread]
+constexpr int64_t storeall_w_elems(int E) {
+    return (int64_t)MAXC * E * NP * ((E * E + 63) / 64 * 64);
+}
 constexpr int64_t storeall_slot_elems(int K, int E) {
-    return (int64_t)K * E * E * E + storeall_proj_elems(K) + (int64_t)E * E * E;
+    return (int64_t)K * E * E * E + storeall_proj_elems(K) + (int64_t)E * E * E +
+           storeall_w_elems(E);
 }
 constexpr int SCAN_BLOCK = 256;
 

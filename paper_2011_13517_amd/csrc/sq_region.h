@@ -18,7 +18,6 @@ struct Slot {              // an atom touching the current box
 // Column path of the projector block: every thread handles the pieces of
 // atom supports that cross its own z-pencil.  An entry names the atom slot,
 // the first support row of the piece and its z range in the box.
-constexpr int MAXC = 4;    // supports crossing one pencil of a box
 struct ColEntry {
     int32_t slot, row0, zlo, n;
 };
@@ -569,21 +568,54 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
 //      add the projector term to the own pencil, reload it.
 // cur is written to LDS at the start even when the previous step left the
 // same values there: a conditional store costs more registers than it saves.
-// (st: see local_part_lowreg; LOWREG steps only)
-template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
-          bool LOWREG = false>
-__device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
-                                                const T (&d)[DREG ? E : 1], int64_t col,
-                                                int64_t plane, int gz0, int n2, T (&cur)[E],
-                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first,
-                                                T *st = nullptr) {
+// A per-row update the store-all adjoint runs inside a step, right after the
+// projections of cur (the own pencil in LDS holds cur; the projection buffer
+// of the previous step is still intact there).
+template <typename T>
+struct WArgs {
+    const T *ck;     // the region's stored vectors
+    T *wb;           // accumulator rows
+    int kp;          // p-term: projections chi . v_kp of the forward sweep ...
+    T ap;            //   ... weight, times the own pencil
+    int kq;          // q-term (kq >= 0): projection buffer parq of nl ...
+    T aq;            //   ... weight, times v_kq
+    int parq;
+};
+
+template <typename T, int E, int BLOCK>
+__device__ __forceinline__ void w_update(const RegionArgs<T> &a, const ColNL<T> &nl,
+                                         const WArgs<T> &w, const T *mine);
+
+// First half of a step (up to the second barrier): publish cur, project it,
+// local part of prev.  (st: see local_part_lowreg; LOWREG steps only.)
+template <typename T, int E, int R, int ZS, bool DREG, bool GRAD, bool LOWREG, int BLOCK = 64,
+          bool WH = false>
+__device__ __forceinline__ void step_col_a(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                           const T (&d)[DREG ? E : 1], int64_t col,
+                                           int64_t plane, int gz0, int n2, T (&cur)[E],
+                                           T (&prev)[E], T *lds, ColNL<T> &nl,
+                                           T *st = nullptr, const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    if constexpr (WH) {
+        if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
+    }
     if constexpr (LOWREG)
         local_part_lowreg<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds, st);
     else
         local_part<T, E, R, ZS, DREG>(a, c, d, col, plane, gz0, n2, cur, prev, lds);
+}
+
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD,
+          bool LOWREG = false, bool WH = false>
+__device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
+                                                const T (&d)[DREG ? E : 1], int64_t col,
+                                                int64_t plane, int gz0, int n2, T (&cur)[E],
+                                                T (&prev)[E], T *lds, ColNL<T> &nl, bool first,
+                                                T *st = nullptr, const WArgs<T> *w = nullptr) {
+    step_col_a<T, E, R, ZS, DREG, GRAD, LOWREG, BLOCK, WH>(a, c, d, col, plane, gz0, n2, cur,
+                                                           prev, lds, nl, st, w);
     __syncthreads();
     if (first) {
 #pragma unroll
@@ -603,15 +635,63 @@ __device__ __forceinline__ void region_step_col(const RegionArgs<T> &a, const St
 }
 
 // projections of one vector without a recurrence step (column path)
-template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD>
+template <typename T, int E, int R, int ZS, int BLOCK, bool GRAD, bool WH = false>
 __device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const StepCtx<T, E, R> &c,
-                                              const T (&vec)[E], ColNL<T> &nl) {
+                                              const T (&vec)[E], ColNL<T> &nl,
+                                              const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
     __syncthreads();
     if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    if constexpr (WH) {
+        if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
+    }
     __syncthreads();
     col_zero_next<T, BLOCK, GRAD>(nl, c.nat);
     nl.par ^= 1;
+}
+
+// W(y) += ap p_kp vt(y) + aq q v_kq(y) on the rows of this thread's column
+// pieces; rows are handled in batches (loads first, then the FMAs).
+template <typename T, int E, int BLOCK>
+__device__ __forceinline__ void w_update(const RegionArgs<T> &a, const ColNL<T> &nl,
+                                         const WArgs<T> &w, const T *mine) {
+    constexpr int EE = E * E;
+    constexpr int NB = 4;
+    const uint32_t t = threadIdx.x;
+    const T *pk = w.ck + (int64_t)a.K * E * EE + (int64_t)w.kp * MAX_REGION_ATOMS * 4 * NP;
+    const bool hq = w.kq >= 0;
+    const T *vk = w.ck + (int64_t)(hq ? w.kq : 0) * E * EE + t;
+    for (int cc = 0; cc < nl.ncol; ++cc) {
+        const ColEntry e = nl.cols[cc];
+        T q[NP], p[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+            p[l] = w.ap * pk[e.slot * 4 * NP + l];
+            q[l] = hq ? w.aq * nl.pacc[((int64_t)w.parq * nl.maxat + e.slot) * NP + l] : (T)0;
+        }
+        T *wc = w.wb + (int64_t)cc * E * NP * BLOCK + t;
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            T tv[NB], vv[NB], wv[NB][NP];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);
+                tv[b] = mine[e.zlo + i];
+                vv[b] = hq ? vk[(int64_t)(e.zlo + i) * EE] : (T)0;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) wv[b][l] = wc[((int64_t)i * NP + l) * BLOCK];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (i0 + b < e.n) {
+#pragma unroll
+                    for (int l = 0; l < NP; ++l)
+                        wc[((int64_t)(i0 + b) * NP + l) * BLOCK] =
+                            wv[b][l] + p[l] * tv[b] + q[l] * vv[b];
+                }
+            }
+        }
+    }
 }
 
 template <typename T, int E>
