@@ -197,48 +197,19 @@ __device__ __forceinline__ void adjoint_rstep_col(const AdjointArgs<T> &aa,
 
 // G += alpha vt_{k+1} v_k with v_k read from its stored slot.  All loads are
 // issued before the FMAs (one memory wait; left alone, the allocator issues
-// load, wait, FMA per z).  With GHBM the accumulator is the slot's
-// [z][pencil] array gb (L2-resident) instead of registers.
-template <typename T, int E, bool GHBM, typename Ctx>
-__device__ __forceinline__ void sa_gupdate(const Ctx &c, const T *ck, T *gb, int k, T alpha,
-                                           const T (&ta)[E], T (&G)[GHBM ? 1 : E]) {
+// load, wait, FMA per z).
+template <typename T, int E, typename Ctx>
+__device__ __forceinline__ void sa_gupdate(const Ctx &c, const T *ck, int k, T alpha,
+                                           const T (&ta)[E], T (&G)[E]) {
     constexpr int EE = E * E;
-    if (c.active) {
-        const uint32_t t = threadIdx.x;
-        if constexpr (GHBM) {
-            constexpr int CH = E;
+    if (!c.active) return;
+    const uint32_t t = threadIdx.x;
+    T vk[E];
 #pragma unroll
-            for (int z0 = 0; z0 < E; z0 += CH) {
-                T vk[CH], g[CH];
+    for (int z = 0; z < E; ++z) vk[z] = sgpr_ptr(ck + ((int64_t)k * E + z) * EE)[t];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    if (z0 + i < E) {
-                        vk[i] = sgpr_ptr(ck + ((int64_t)k * E + z0 + i) * EE)[t];
-                        g[i] = sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t];
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    if (z0 + i < E) sgpr_ptr(gb + (int64_t)(z0 + i) * EE)[t] = g[i] + alpha * ta[z0 + i] * vk[i];
-            }
-        } else {
-            // all loads first, then the FMAs: one memory wait instead of one
-            // per z (left alone, the allocator serialises the loads)
-            constexpr int CH = E;
-#pragma unroll
-            for (int z0 = 0; z0 < E; z0 += CH) {
-                T vk[CH];
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    if (z0 + i < E) vk[i] = sgpr_ptr(ck + ((int64_t)k * E + z0 + i) * EE)[t];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    if (z0 + i < E) G[z0 + i] += alpha * ta[z0 + i] * vk[i];
-            }
-        }
-    }
+    for (int z = 0; z < E; ++z) G[z] += alpha * ta[z] * vk[z];
 }
 
 // Reverse step when the forward pass stored every v_k (checkpoint stride 1):
@@ -246,19 +217,17 @@ __device__ __forceinline__ void sa_gupdate(const Ctx &c, const T *ck, T *gb, int
 // it is used (the G update) instead of being held as a register pencil, so only
 // vt_{k+1}, vt_{k+2} and G stay resident; the projections of v_k needed for dR
 // were stored by the forward sweep next to the vectors.
-// With GHBM the accumulator G lives in the slot (gb, [z][pencil], L2-resident)
-// and is updated in chunks of loads then stores, instead of in registers.
-template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD, bool GHBM>
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GRAD>
 __device__ __forceinline__ void adjoint_rstep_sa(const AdjointArgs<T> &aa,
                                                  const StepCtx<T, E, R> &c, const AdjNode &nd,
                                                  const T (&d)[DREG ? E : 1], T *lds, ColNL<T> &nlA,
                                                  const Slot *slots, double (*dRacc)[3],
-                                                 const T *ck, T *gb, int k, T (&ta)[E],
-                                                 T (&tb)[E], T (&G)[GHBM ? 1 : E], double tau) {
+                                                 const T *ck, int k, T (&ta)[E], T (&tb)[E],
+                                                 T (&G)[E], double tau) {
     const RegionArgs<T> &a = aa.g;
     constexpr int EE = E * E;
     const T alpha = k == 0 ? (T)1 : (T)2;
-    sa_gupdate<T, E, GHBM>(c, ck, gb, k, alpha, ta, G);
+    sa_gupdate<T, E>(c, ck, k, alpha, ta, G);
     if (k >= 1) {
         region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, true>(
             a, c, d, nd.col, nd.plane, nd.gz0, nd.n2, ta, tb, lds, nlA, false);
@@ -371,15 +340,15 @@ __device__ __forceinline__ void w_contract(const RegionArgs<T> &a, const ColNL<T
 // (own pencil vt_{k+1} after its first barrier, the projection buffer of step
 // k+1 still holding q_{k+1}) adds alpha_k p_k vt_{k+1} + alpha_{k+1} q_{k+1} v_{k+1};
 // the last term alpha_0 q_0 v_0 is added after the k = 0 projections.
-template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG, bool GHBM>
+template <typename T, int E, int R, int ZS, int BLOCK, bool MASKZ, bool DREG>
 __device__ __forceinline__ void adjoint_rstep_saw(const AdjointArgs<T> &aa,
                                                   const StepCtx<T, E, R> &c, const AdjNode &nd,
                                                   const T (&d)[DREG ? E : 1], T *lds,
-                                                  ColNL<T> &nlA, const T *ck, T *gb, T *wb, int k,
-                                                  T (&ta)[E], T (&tb)[E], T (&G)[GHBM ? 1 : E]) {
+                                                  ColNL<T> &nlA, const T *ck, T *wb, int k,
+                                                  T (&ta)[E], T (&tb)[E], T (&G)[E]) {
     const RegionArgs<T> &a = aa.g;
     const T alpha = k == 0 ? (T)1 : (T)2;
-    sa_gupdate<T, E, GHBM>(c, ck, gb, k, alpha, ta, G);
+    sa_gupdate<T, E>(c, ck, k, alpha, ta, G);
     WArgs<T> w{ck, wb, k, alpha, k + 1 <= a.K - 1 ? k + 1 : -1, (T)2, nlA.par ^ 1};
     if (k >= 1) {
         region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, true, true>(
@@ -419,10 +388,6 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
     constexpr int CA = COLNL ? AT : 1;
     constexpr int CG = (COLNL && GRAD && !WM) ? AT : 1;
     constexpr bool DREG = sizeof(T) == 4 ? E <= 21 : E <= 13;
-    // store-all kernels with dR whose pencils do not fit the registers keep the
-    // dV accumulator in their slot instead
-    constexpr bool GHBM = COLNL && STOREALL && GRAD &&
-                          ((sizeof(T) == 4 && E >= 27) || (sizeof(T) == 8 && E >= 17));
     constexpr int EE = E * E;
     const RegionArgs<T> &a = aa.g;
 
@@ -555,9 +520,8 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             __syncthreads();
         }
 
-        T v[E], G[GHBM ? 1 : E];
-        T *gb = ck + (int64_t)K * E * E * E + storeall_proj_elems(K);
-        T *wb = gb + (int64_t)E * E * E;
+        T v[E], G[E];
+        T *wb = ck + (int64_t)K * E * E * E + storeall_proj_elems(K);
         if constexpr (COLNL && STOREALL) {
             // ---- forward storing v_0 .. v_{K-1}; reverse reads them back ----
             T w[E];
@@ -609,28 +573,24 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             for (int z = 0; z < E; ++z) {
                 t1[z] = (is_ctr && z == cz0) ? aK : (T)0;
                 t2[z] = (T)0;
-                if constexpr (GHBM) {
-                    if (c.active) sgpr_ptr(gb + (int64_t)z * EE)[(uint32_t)tid] = (T)0;
-                } else {
-                    G[z] = (T)0;
-                }
+                G[z] = (T)0;
             }
             if constexpr (WM) {
                 for (int k = K - 1; k >= 0; k -= 2) {
-                    adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG, GHBM>(
-                        aa, c, nd, d, lds, nlA, ck, gb, wb, k, t1, t2, G);
+                    adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG>(
+                        aa, c, nd, d, lds, nlA, ck, wb, k, t1, t2, G);
                     if (k - 1 >= 0)
-                        adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG, GHBM>(
-                            aa, c, nd, d, lds, nlA, ck, gb, wb, k - 1, t2, t1, G);
+                        adjoint_rstep_saw<T, E, R, ZS, BLOCK, MASKZ, DREG>(
+                            aa, c, nd, d, lds, nlA, ck, wb, k - 1, t2, t1, G);
                 }
                 w_contract<T, E, BLOCK>(a, nlA, slots, wb, cdR, a.h3 / tau);
             } else {
                 for (int k = K - 1; k >= 0; k -= 2) {
-                    adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
-                        aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k, t1, t2, G, tau);
+                    adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                        aa, c, nd, d, lds, nlA, slots, cdR, ck, k, t1, t2, G, tau);
                     if (k - 1 >= 0)
-                        adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD, GHBM>(
-                            aa, c, nd, d, lds, nlA, slots, cdR, ck, gb, k - 1, t2, t1, G, tau);
+                        adjoint_rstep_sa<T, E, R, ZS, BLOCK, MASKZ, DREG, GRAD>(
+                            aa, c, nd, d, lds, nlA, slots, cdR, ck, k - 1, t2, t1, G, tau);
                 }
             }
         } else {
@@ -715,10 +675,7 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                 if (z < c.dz) {
                     int gz = gz0 + z;
                     gz = gz >= n2 ? gz - n2 : gz;
-                    T gz_val;
-                    if constexpr (GHBM) gz_val = sgpr_ptr(gb + (int64_t)z * EE)[(uint32_t)tid];
-                    else gz_val = G[z];
-                    unsafeAtomicAdd(aa.dV + col + plane * gz, (double)gz_val * itau);
+                    unsafeAtomicAdd(aa.dV + col + plane * gz, (double)G[z] * itau);
                 }
             }
         }

@@ -14,9 +14,8 @@ constexpr int MAX_R = 6;       // largest FD radius supported (order 12)
 constexpr int LDS_BYTES = 163840;   // gfx950: 160 KiB of LDS per workgroup
 constexpr int MAX_REGION_ATOMS = 128;  // cap on the atom list of one region box
 // store-all adjoint slot: v_0..v_{K-1} ([k][z][pencil]), then the projections
-// (chi . v_k, dchi/dR . v_k) of every atom of the box ([k][atom][4 NP]), then
-// the dV accumulator of the box ([z][pencil]) for kernels that keep it in
-// memory rather than in registers
+// (chi . v_k, and dchi/dR . v_k where formed) of every atom of the box
+// ([k][atom][4 NP]), then the dR row accumulators W
 constexpr int64_t storeall_proj_elems(int K) { return (int64_t)K * MAX_REGION_ATOMS * 4 * NP; }
 constexpr int MAXC = 4;    // atom supports crossing one pencil of a box
 // dR accumulators W of the store-all adjoint: [column][row in the piece][NP][thread]
@@ -24,8 +23,7 @@ constexpr int64_t storeall_w_elems(int E) {
     return (int64_t)MAXC * E * NP * ((E * E + 63) / 64 * 64);
 }
 constexpr int64_t storeall_slot_elems(int K, int E) {
-    return (int64_t)K * E * E * E + storeall_proj_elems(K) + (int64_t)E * E * E +
-           storeall_w_elems(E);
+    return (int64_t)K * E * E * E + storeall_proj_elems(K) + storeall_w_elems(E);
 }
 constexpr int SCAN_BLOCK = 256;
 
