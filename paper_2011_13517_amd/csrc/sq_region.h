@@ -395,14 +395,64 @@ __device__ __forceinline__ int build_columns(const RegionArgs<T> &a, const Slot 
 
 // raw projections of this thread's pencil (in LDS) onto the crossing supports,
 // reduced over the box with LDS atomics into the current parity buffer
+// Lanes l and l ^ m (m = 1, 2) that add into the same atom slot merge their
+// values first (DPP quad permutes, no LDS): the lane with bit m clear keeps
+// the sum, the other drops out.  Neighbouring pencils usually cross the same
+// atoms in the same order, so this cuts the same-address conflicts of the LDS
+// atomics that follow by up to four.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T, int NV, int CTRL, int M>
+__device__ __forceinline__ void merge_level(T (&v)[NV], int &slot) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int so = dpp_i<CTRL>(slot);
+    T vo[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vo[i] = dpp_f<CTRL>(v[i]);
+    if (so == slot && slot >= 0) {
+        if (lane & M) {
+            slot = -1;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = (T)0;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] += vo[i];
+        }
+    }
+}
+template <typename T, int NV>
+__device__ __forceinline__ void merge_equal_slots(T (&v)[NV], int &slot) {
+    merge_level<T, NV, 0xB1, 1>(v, slot);   // quad_perm(1,0,3,2): partner lane ^ 1
+    merge_level<T, NV, 0x4E, 2>(v, slot);   // quad_perm(2,3,0,1): partner lane ^ 2
+}
+
 // The support rows of a column piece are read in batches of NB (loads of the
 // batch first, then its FMAs), so one L2 round trip serves NB rows.
 template <typename T, bool GRAD>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
                                          const T *pencil) {
     constexpr int NB = GRAD ? 2 : 4;
-    for (int c = 0; c < nl.ncol; ++c) {
-        const ColEntry e = nl.cols[c];
+    // every lane runs the wave's largest column count (the DPP merge needs its
+    // partner lanes active); lanes past their own count contribute nothing
+    int ncw = nl.ncol;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ncw = max(ncw, __shfl_xor(ncw, m));
+    for (int c = 0; c < ncw; ++c) {
+        const bool has = c < nl.ncol;
+        const ColEntry e = has ? nl.cols[c] : ColEntry{-1, 0, 0, 0};
         T s[NP] = {0, 0, 0, 0};
         T g[GRAD ? 3 * NP : 1];
         if constexpr (GRAD) {
@@ -435,13 +485,30 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
                 }
             }
         }
-        T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
-#pragma unroll
-        for (int l = 0; l < NP; ++l) atomicAdd(&pa[l], s[l]);
+        int slot = e.slot;
         if constexpr (GRAD) {
-            T *ga = nl.gacc + ((int64_t)nl.par * nl.maxat + e.slot) * 3 * NP;
+            T sg[NP + 3 * NP];
 #pragma unroll
-            for (int q = 0; q < 3 * NP; ++q) atomicAdd(&ga[q], g[q]);
+            for (int l = 0; l < NP; ++l) sg[l] = s[l];
+#pragma unroll
+            for (int q = 0; q < 3 * NP; ++q) sg[NP + q] = g[q];
+            merge_equal_slots<T, 4 * NP>(sg, slot);
+#pragma unroll
+            for (int l = 0; l < NP; ++l) s[l] = sg[l];
+#pragma unroll
+            for (int q = 0; q < 3 * NP; ++q) g[q] = sg[NP + q];
+        } else {
+            merge_equal_slots<T, NP>(s, slot);
+        }
+        if (slot >= 0) {
+            T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + slot) * NP;
+#pragma unroll
+            for (int l = 0; l < NP; ++l) atomicAdd(&pa[l], s[l]);
+            if constexpr (GRAD) {
+                T *ga = nl.gacc + ((int64_t)nl.par * nl.maxat + slot) * 3 * NP;
+#pragma unroll
+                for (int q = 0; q < 3 * NP; ++q) atomicAdd(&ga[q], g[q]);
+            }
         }
     }
 }
@@ -597,7 +664,7 @@ __device__ __forceinline__ void step_col_a(const RegionArgs<T> &a, const StepCtx
                                            T *st = nullptr, const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
-    if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    col_dots<T, GRAD>(a, nl, c.mine);   // all lanes: the merge exchanges between them
     if constexpr (WH) {
         if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
     }
@@ -641,7 +708,7 @@ __device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const Step
                                               const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
     __syncthreads();
-    if (nl.ncol) col_dots<T, GRAD>(a, nl, c.mine);
+    col_dots<T, GRAD>(a, nl, c.mine);   // all lanes: the merge exchanges between them
     if constexpr (WH) {
         if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
     }
