@@ -295,7 +295,7 @@ __device__ __forceinline__ void store_projections(const ColNL<T> &nl, int nat, T
 // (vt_{k+1} . chi)(dchi . v_k)] equals dchi . W with
 // W(y) = sum_k alpha_k (p_k vt_{k+1}(y) + q_k v_k(y)) on the support rows.  W is
 // accumulated per row of the thread's column pieces (in the slot,
-// [column][row][l][thread]) inside the reverse steps, and contracted with
+// [column][row][thread][l]) inside the reverse steps, and contracted with
 // dchi once per region, so no dchi projections are formed per step.
 // contraction of W with dchi/dR into the per-atom accumulators of the box
 template <typename T, int E, int BLOCK>
@@ -309,18 +309,19 @@ __device__ __forceinline__ void w_contract(const RegionArgs<T> &a, const ColNL<T
         double cj[NP];
 #pragma unroll
         for (int l = 0; l < NP; ++l) cj[l] = a.cJ[(int64_t)slots[e.slot].atom * NP + l];
-        const T *wc = wb + (int64_t)cc * E * NP * BLOCK + t;
+        const WVec<T> *wc = reinterpret_cast<const WVec<T> *>(wb) + ((int64_t)cc * E * BLOCK + t);
         double sx[3] = {0.0, 0.0, 0.0};
         for (int i0 = 0; i0 < e.n; i0 += NB) {
-            T dc[NB][3 * NP], wv[NB][NP];
+            T dc[NB][3 * NP];
+            WVec<T> wv[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int i = min(i0 + b, e.n - 1);
                 const T *dcp = a.dchi + (int64_t)(e.row0 + i) * 3 * NP;
 #pragma unroll
                 for (int q = 0; q < 3 * NP; ++q) dc[b][q] = dcp[q];
-#pragma unroll
-                for (int l = 0; l < NP; ++l) wv[b][l] = i0 + b < e.n ? wc[((int64_t)i * NP + l) * BLOCK] : (T)0;
+                wv[b] = wc[(int64_t)i * BLOCK];
+                if (i0 + b >= e.n) wv[b] = WVec<T>{{0, 0, 0, 0}};
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -329,7 +330,7 @@ __device__ __forceinline__ void w_contract(const RegionArgs<T> &a, const ColNL<T
                 for (int l = 0; l < NP; ++l)
 #pragma unroll
                     for (int x = 0; x < 3; ++x)
-                        sx[x] += cj[l] * (double)dc[b][l * 3 + x] * (double)wv[b][l];
+                        sx[x] += cj[l] * (double)dc[b][l * 3 + x] * (double)wv[b].v[l];
         }
 #pragma unroll
         for (int x = 0; x < 3; ++x) atomicAdd(&cdR[e.slot][x], sx[x] * scale);
@@ -521,7 +522,7 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
         }
 
         T v[E], G[E];
-        T *wb = ck + (int64_t)K * E * E * E + storeall_proj_elems(K);
+        T *wb = ck + storeall_w_offset(K, E);
         if constexpr (COLNL && STOREALL) {
             // ---- forward storing v_0 .. v_{K-1}; reverse reads them back ----
             T w[E];
@@ -562,9 +563,8 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                 for (int cc = 0; cc < nlA.ncol; ++cc) {
                     const ColEntry e = nlA.cols[cc];
                     for (int i = 0; i < e.n; ++i)
-#pragma unroll
-                        for (int l = 0; l < NP; ++l)
-                            wb[(((int64_t)cc * E + i) * NP + l) * BLOCK + tid] = (T)0;
+                        reinterpret_cast<WVec<T> *>(wb)[((int64_t)cc * E + i) * BLOCK + tid] =
+                            WVec<T>{{0, 0, 0, 0}};
                 }
             }
             T t1[E], t2[E];

@@ -768,6 +768,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
             if (c.storeall) st = std::max<int64_t>(st, storeall_slot_elems(c.K, g.E));
             c.ckpt_stride = std::max(c.ckpt_stride, st);
         }
+        c.ckpt_stride = round_np(c.ckpt_stride);   // slots stay NP-vector aligned
         const size_t n = (size_t)max_grid * c.ckpt_stride;
         if (c.aprec == SQ_FP64) {
             double *q = nullptr;

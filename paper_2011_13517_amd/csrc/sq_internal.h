@@ -18,12 +18,17 @@ constexpr int MAX_REGION_ATOMS = 128;  // cap on the atom list of one region box
 // ([k][atom][4 NP]), then the dR row accumulators W
 constexpr int64_t storeall_proj_elems(int K) { return (int64_t)K * MAX_REGION_ATOMS * 4 * NP; }
 constexpr int MAXC = 4;    // atom supports crossing one pencil of a box
-// dR accumulators W of the store-all adjoint: [column][row in the piece][NP][thread]
+// dR accumulators W of the store-all adjoint: [column][row in the piece][thread][NP],
+// NP-vector aligned (the slot stride and the W offset are multiples of NP)
 constexpr int64_t storeall_w_elems(int E) {
     return (int64_t)MAXC * E * NP * ((E * E + 63) / 64 * 64);
 }
+constexpr int64_t round_np(int64_t n) { return (n + NP - 1) / NP * NP; }
+constexpr int64_t storeall_w_offset(int K, int E) {
+    return round_np((int64_t)K * E * E * E + storeall_proj_elems(K));
+}
 constexpr int64_t storeall_slot_elems(int K, int E) {
-    return (int64_t)K * E * E * E + storeall_proj_elems(K) + storeall_w_elems(E);
+    return storeall_w_offset(K, E) + storeall_w_elems(E);
 }
 constexpr int SCAN_BLOCK = 256;
 

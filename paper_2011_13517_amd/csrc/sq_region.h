@@ -638,6 +638,14 @@ __device__ __forceinline__ void local_part_lowreg(const RegionArgs<T> &a,
 // A per-row update the store-all adjoint runs inside a step, right after the
 // projections of cur (the own pencil in LDS holds cur; the projection buffer
 // of the previous step is still intact there).
+// NP-vector of W (one support row, all projectors), moved as one aligned unit
+template <typename T>
+struct alignas(4 * sizeof(T)) WVec {
+    T v[4];
+    __device__ T &operator[](int i) { return v[i]; }
+};
+static_assert(NP == 4, "WVec holds NP values");
+
 template <typename T>
 struct WArgs {
     const T *ck;     // the region's stored vectors
@@ -664,7 +672,8 @@ __device__ __forceinline__ void step_col_a(const RegionArgs<T> &a, const StepCtx
                                            T *st = nullptr, const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, cur);
     __syncthreads();
-    col_dots<T, GRAD>(a, nl, c.mine);   // all lanes: the merge exchanges between them
+    // all lanes of the block (c.nat is uniform): the merge exchanges between lanes
+    if (c.nat) col_dots<T, GRAD>(a, nl, c.mine);
     if constexpr (WH) {
         if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
     }
@@ -708,7 +717,8 @@ __device__ __forceinline__ void col_dots_only(const RegionArgs<T> &a, const Step
                                               const WArgs<T> *w = nullptr) {
     if (c.active) store_pencil<T, E, ZS>(c.mine, vec);
     __syncthreads();
-    col_dots<T, GRAD>(a, nl, c.mine);   // all lanes: the merge exchanges between them
+    // all lanes of the block (c.nat is uniform): the merge exchanges between lanes
+    if (c.nat) col_dots<T, GRAD>(a, nl, c.mine);
     if constexpr (WH) {
         if (nl.ncol) w_update<T, E, BLOCK>(a, nl, *w, c.mine);
     }
@@ -736,25 +746,26 @@ __device__ __forceinline__ void w_update(const RegionArgs<T> &a, const ColNL<T> 
             p[l] = w.ap * pk[e.slot * 4 * NP + l];
             q[l] = hq ? w.aq * nl.pacc[((int64_t)w.parq * nl.maxat + e.slot) * NP + l] : (T)0;
         }
-        T *wc = w.wb + (int64_t)cc * E * NP * BLOCK + t;
+        // row i of this piece: one NP-vector per thread, wc[i * BLOCK]
+        WVec<T> *wc = reinterpret_cast<WVec<T> *>(w.wb) + ((int64_t)cc * E * BLOCK + t);
         for (int i0 = 0; i0 < e.n; i0 += NB) {
-            T tv[NB], vv[NB], wv[NB][NP];
+            T tv[NB], vv[NB];
+            WVec<T> wv[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int i = min(i0 + b, e.n - 1);
                 tv[b] = mine[e.zlo + i];
                 vv[b] = hq ? vk[(int64_t)(e.zlo + i) * EE] : (T)0;
-#pragma unroll
-                for (int l = 0; l < NP; ++l) wv[b][l] = wc[((int64_t)i * NP + l) * BLOCK];
+                wv[b] = wc[(int64_t)i * BLOCK];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if (i0 + b < e.n) {
+                    WVec<T> r = wv[b];
 #pragma unroll
-                    for (int l = 0; l < NP; ++l)
-                        wc[((int64_t)(i0 + b) * NP + l) * BLOCK] =
-                            wv[b][l] + p[l] * tv[b] + q[l] * vv[b];
+                    for (int l = 0; l < NP; ++l) r[l] += p[l] * tv[b] + q[l] * vv[b];
+                    wc[(int64_t)(i0 + b) * BLOCK] = r;
                 }
             }
         }
