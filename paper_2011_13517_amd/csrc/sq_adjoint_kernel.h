@@ -538,14 +538,27 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
             // step; the last vector v_{K-1} is stored after the loop.
             constexpr int E3 = E * E * E;
             // In W mode (dR) only the value projections chi . v_k are kept.
+            // The forward sweep holds two pencils only, so it keeps the
+            // diagonal in registers even where the reverse sweep cannot.
             constexpr bool FG = GRAD && !WM;
+            T dF[E];
+#pragma unroll
+            for (int z = 0; z < E; ++z) {
+                if constexpr (DREG) {
+                    dF[z] = d[z];
+                } else {
+                    int gz = gz0 + z;
+                    gz = gz >= n2 ? gz - n2 : gz;
+                    dF[z] = (c.active && z < c.dz) ? a.D[col + plane * gz] : (T)0;
+                }
+            }
             for (int k = 0; k + 1 <= K - 1; k += 2) {
-                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, FG, true>(
-                    a, c, d, col, plane, gz0, n2, v, w, lds, nlB, k == 0, ck + (int64_t)k * E3);
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, true, FG, true>(
+                    a, c, dF, col, plane, gz0, n2, v, w, lds, nlB, k == 0, ck + (int64_t)k * E3);
                 if constexpr (GRAD) store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, k);
                 if (k + 2 <= K - 1) {
-                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, FG, true>(
-                        a, c, d, col, plane, gz0, n2, w, v, lds, nlB, false,
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, true, FG, true>(
+                        a, c, dF, col, plane, gz0, n2, w, v, lds, nlB, false,
                         ck + (int64_t)(k + 1) * E3);
                     if constexpr (GRAD) store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, k + 1);
                 }
