@@ -295,7 +295,8 @@ __device__ __forceinline__ void store_projections(const ColNL<T> &nl, int nat, T
 // (vt_{k+1} . chi)(dchi . v_k)] equals dchi . W with
 // W(y) = sum_k alpha_k (p_k vt_{k+1}(y) + q_k v_k(y)) on the support rows.  W is
 // accumulated per row of the thread's column pieces (in the slot,
-// [column][row][thread][l]) inside the reverse steps, and contracted with
+// [row][thread][l], the thread's rows numbered densely over its pieces) inside
+// the reverse steps, and contracted with
 // dchi once per region, so no dchi projections are formed per step.
 // contraction of W with dchi/dR into the per-atom accumulators of the box
 template <typename T, int E, int BLOCK>
@@ -304,12 +305,14 @@ __device__ __forceinline__ void w_contract(const RegionArgs<T> &a, const ColNL<T
                                            double scale) {
     constexpr int NB = 2;
     const uint32_t t = threadIdx.x;
+    int ebase = 0;
     for (int cc = 0; cc < nl.ncol; ++cc) {
         const ColEntry e = nl.cols[cc];
         double cj[NP];
 #pragma unroll
         for (int l = 0; l < NP; ++l) cj[l] = a.cJ[(int64_t)slots[e.slot].atom * NP + l];
-        const WVec<T> *wc = reinterpret_cast<const WVec<T> *>(wb) + ((int64_t)cc * E * BLOCK + t);
+        const WVec<T> *wc = reinterpret_cast<const WVec<T> *>(wb) + ((int64_t)ebase * BLOCK + t);
+        ebase += e.n;
         double sx[3] = {0.0, 0.0, 0.0};
         for (int i0 = 0; i0 < e.n; i0 += NB) {
             T dc[NB][3 * NP];
@@ -572,12 +575,15 @@ cheb_adjoint_kernel(const AdjointArgs<T> aa) {
                 store_projections<T, BLOCK, FG>(nlB, c.nat, ck, K, E3, K - 1);
             }
             if constexpr (WM) {
-                // zero the W rows of this thread's column pieces
+                // zero the W rows of this thread's column pieces (numbered
+                // densely over its pieces: row ebase + i of piece cc)
+                int ebase = 0;
                 for (int cc = 0; cc < nlA.ncol; ++cc) {
                     const ColEntry e = nlA.cols[cc];
                     for (int i = 0; i < e.n; ++i)
-                        reinterpret_cast<WVec<T> *>(wb)[((int64_t)cc * E + i) * BLOCK + tid] =
+                        reinterpret_cast<WVec<T> *>(wb)[(int64_t)(ebase + i) * BLOCK + tid] =
                             WVec<T>{{0, 0, 0, 0}};
+                    ebase += e.n;
                 }
             }
             T t1[E], t2[E];

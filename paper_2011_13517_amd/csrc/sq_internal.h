@@ -18,7 +18,8 @@ constexpr int MAX_REGION_ATOMS = 128;  // cap on the atom list of one region box
 // ([k][atom][4 NP]), then the dR row accumulators W
 constexpr int64_t storeall_proj_elems(int K) { return (int64_t)K * MAX_REGION_ATOMS * 4 * NP; }
 constexpr int MAXC = 4;    // atom supports crossing one pencil of a box
-// dR accumulators W of the store-all adjoint: [column][row in the piece][thread][NP],
+// dR accumulators W of the store-all adjoint: [row][thread][NP] (a thread's rows
+// numbered densely over its column pieces, at most MAXC * E),
 // NP-vector aligned (the slot stride and the W offset are multiples of NP)
 constexpr int64_t storeall_w_elems(int E) {
     return (int64_t)MAXC * E * NP * ((E * E + 63) / 64 * 64);

@@ -738,6 +738,7 @@ __device__ __forceinline__ void w_update(const RegionArgs<T> &a, const ColNL<T> 
     const T *pk = w.ck + (int64_t)a.K * E * EE + (int64_t)w.kp * MAX_REGION_ATOMS * 4 * NP;
     const bool hq = w.kq >= 0;
     const T *vk = w.ck + (int64_t)(hq ? w.kq : 0) * E * EE + t;
+    int ebase = 0;   // this thread's rows are numbered densely over its pieces
     for (int cc = 0; cc < nl.ncol; ++cc) {
         const ColEntry e = nl.cols[cc];
         T q[NP], p[NP];
@@ -747,7 +748,8 @@ __device__ __forceinline__ void w_update(const RegionArgs<T> &a, const ColNL<T> 
             q[l] = hq ? w.aq * nl.pacc[((int64_t)w.parq * nl.maxat + e.slot) * NP + l] : (T)0;
         }
         // row i of this piece: one NP-vector per thread, wc[i * BLOCK]
-        WVec<T> *wc = reinterpret_cast<WVec<T> *>(w.wb) + ((int64_t)cc * E * BLOCK + t);
+        WVec<T> *wc = reinterpret_cast<WVec<T> *>(w.wb) + ((int64_t)ebase * BLOCK + t);
+        ebase += e.n;
         for (int i0 = 0; i0 < e.n; i0 += NB) {
             T tv[NB], vv[NB];
             WVec<T> wv[NB];
