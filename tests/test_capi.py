@@ -53,7 +53,8 @@ def _params(**kw):
 
 @pytest.mark.parametrize("kw", [dict(fd_order=3), dict(fd_order=14), dict(order=0),
                                 dict(kT=0.0), dict(bc=7), dict(precision=5), dict(h=[0.5, 0, 0.5]),
-                                dict(n=[8, 0, 8]), dict(rcut=[-1, 2, 2])])
+                                dict(n=[8, 0, 8]), dict(rcut=[-1, 2, 2]), dict(ckpt_every=-1),
+                                dict(adjoint_precision=3), dict(tune=2), dict(tune=-1)])
 def test_invalid_params_rejected(lib, kw):
     ctx = C.c_void_p()
     st = lib.sq_setup(C.byref(_params(**kw)), None, None, None, 512, C.byref(ctx))
@@ -87,3 +88,18 @@ def test_package_has_no_fallback_path():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "sq_oracle" not in txt, f
+
+
+def _struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "sq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", src).group(1)
+    return [m.group(2) for m in
+            re.finditer(r"\b(int32_t|int64_t|double|const [a-z0-9_]+ \*)\s*([A-Za-z_0-9]+)", body)]
+
+
+@pytest.mark.parametrize("name,cls", [("sq_params", L.sq_params), ("sq_info", L.sq_info),
+                                      ("sq_projectors", L.sq_projectors)])
+def test_binding_struct_layout_matches_header(name, cls):
+    """The ctypes structures list the header's fields in the header's order."""
+    assert _struct_fields(name) == [f[0] for f in cls._fields_]
