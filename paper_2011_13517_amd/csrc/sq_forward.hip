@@ -123,6 +123,9 @@ cheb_forward_kernel(const RegionArgs<T> a) {
             c.nb[4 * (p - 1) + 3] = (c.active && py - p >= 0) ? tid - p * c.dx : npen;
         }
         c.mine = lds + tid * ZS;
+        c.px = px;
+        c.py = py;
+        c.npen = npen;
         __syncthreads();
         c.nat = min(s_nat, MAXAT);
         if (tid == 0 && s_nat > MAXAT) atomicOr(a.status, 1);
