@@ -189,11 +189,12 @@ def node_box(prob, node, m):
     return lo, dim, ctr
 
 
-KIND_G, KIND_U, KIND_DG, KIND_DU = 0, 1, 2, 3
+KIND_G, KIND_U, KIND_DG, KIND_DU, KIND_S = 0, 1, 2, 3, 4
 
 
 def cheb_coeffs(kind, lambda_f, kT, lmin, lmax, K):
-    """c_k (kind 0), d_k (kind 1) and their lambda_f derivatives (kinds 2, 3)."""
+    """c_k (kind 0), d_k (kind 1), their lambda_f derivatives (kinds 2, 3) and the
+    coefficients of the entropy integrand g log g + (1-g) log(1-g) (kind 4)."""
     omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
     out = np.zeros(K + 1)
     N = lib().orc_cheb_coeffs(kind, (lambda_f - omega) / tau, kT / tau, tau, omega, K,
@@ -208,6 +209,16 @@ def contract(mu, c, d):
     lib().orc_contract(mu.ctypes.data, n, K1 - 1, np.ascontiguousarray(c).ctypes.data,
                        np.ascontiguousarray(d).ctypes.data, rho.ctypes.data, u.ctypes.data)
     return rho, u
+
+
+def entropy(mu, lambda_f, kT, lmin, lmax):
+    """Pointwise entropy, Eq. (sq), in units of k_B: s^q = -2 int s(lambda) dmu_q with
+    s = g log g + (1-g) log(1-g), evaluated with the Chebyshev rule as
+    -2 (e_0 mu_0 / 2 + sum_k e_k mu_k).  Returns (s, e)."""
+    mu = np.ascontiguousarray(mu, np.float64)
+    e, _ = cheb_coeffs(KIND_S, lambda_f, kT, lmin, lmax, mu.shape[1] - 1)
+    f, _ = contract(mu, e, e)
+    return -f, e
 
 
 def electron_count(M, lambda_f, kT, lmin, lmax):

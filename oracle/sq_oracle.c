@@ -321,10 +321,17 @@ int orc_node_box(const orc_problem *P, int64_t node, const int32_t m[3],
 /*   kind 1: f = (tau x + omega) g         (band energy integrand, Eq. (uq))    */
 /*   kind 2: f = d g / d lambda_f          (unscaled lambda_f, per Ha)          */
 /*   kind 3: f = (tau x + omega) d g / d lambda_f                               */
+/*   kind 4: f = g log g + (1 - g) log(1 - g)  (entropy integrand, Eq. (sq))     */
 /* g(x) = 1 / (1 + exp((x - lf)/th)) = (1 - tanh((x - lf) / (2 th))) / 2.        */
+/* For kind 4, with t = |x - lf| / th (the integrand is even in x - lf):          */
+/*   g log g + (1 - g) log(1 - g) = -(t e^-t / (1 + e^-t) + log(1 + e^-t)).      */
 /* ------------------------------------------------------------------------- */
 static double integrand(int kind, double x, double lf, double th, double tau, double omega) {
     const double z = (x - lf) / (2.0 * th);
+    if (kind == 4) {
+        const double t = fabs(x - lf) / th, e = exp(-t);
+        return -(t * e / (1.0 + e) + log1p(e));
+    }
     if (kind == 0) return 0.5 * (1.0 - tanh(z));
     if (kind == 1) return (tau * x + omega) * 0.5 * (1.0 - tanh(z));
     const double ch = cosh(z);
@@ -375,7 +382,7 @@ int64_t orc_cheb_coeffs(int kind, double lf_hat, double th_hat, double tau, doub
             if (e > d) d = e;
         }
         if (kind == 1 || kind == 3) sc = fabs(tau) + fabs(omega);   /* size of (tau x + omega) */
-        if (kind >= 2) sc /= tau;                                   /* d/dlambda_f carries 1/tau */
+        if (kind == 2 || kind == 3) sc /= tau;                      /* d/dlambda_f carries 1/tau */
         N = N2;
         memcpy(a, b, sizeof(double) * (K + 1));
         if (d <= 1e-15 * sc || N >= ((int64_t)1 << 24)) break;

@@ -374,6 +374,66 @@ def test_expansion_converges_to_fermi_function_on_eigenvalues():
 
 
 # --------------------------------------------------------------------------- #
+# entropy, Eq. (sq): s^q = -2 int (g log g + (1-g) log(1-g)) dmu_q  (units of k_B)
+# --------------------------------------------------------------------------- #
+def _entropy_integrand(lam, lf, kT):
+    """g log g + (1-g) log(1-g) from g itself (a route independent of the oracle's)."""
+    g = 1.0 / (1.0 + np.exp(np.clip((lam - lf) / kT, -700, 700)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = np.where(g > 0, g * np.log(g), 0.0)
+        b = np.where(g < 1, (1 - g) * np.log1p(-g), 0.0)
+    return a + b
+
+
+def test_entropy_coefficients_vs_adaptive_quadrature():
+    from scipy.integrate import quad
+    lmin, lmax, kT, lf, K = -2.0, 6.0, 0.3, 1.1, 24
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    e, _ = O.cheb_coeffs(O.KIND_S, lf, kT, lmin, lmax, K)
+    for k in (0, 1, 2, 5, 11, 24):
+        f = lambda t: _entropy_integrand(tau * np.cos(t) + omega, lf, kT) * np.cos(k * t)
+        ref = 2.0 / np.pi * quad(f, 0, np.pi, epsabs=1e-15, epsrel=1e-14, limit=400)[0]
+        assert abs(e[k] - ref) < 1e-12, (k, e[k], ref)
+
+
+def test_entropy_of_full_occupation_vanishes():
+    """lambda_f far above the spectrum: g = 1 on [lmin, lmax], so the integrand is 0."""
+    e, _ = O.cheb_coeffs(O.KIND_S, 60.0, 0.1, -2.0, 6.0, 30)
+    assert np.abs(e).max() < 1e-15
+
+
+def test_entropy_single_point_region_closed_form():
+    """A region of one node: H_q is 1x1 and s^q = -2 s(H_qq) exactly in the limit."""
+    prob = synth.small_problem(21, n=(8, 8, 8), rcut=(0, 0, 0), n_atoms=2, rc=1.2)
+    lmin, lmax = _bounds(prob)
+    kT = 0.6
+    lf = 0.5 * (lmin + lmax) - 0.3 * (lmax - lmin)
+    node = 77
+    H, dims, ctr = O.node_dense(prob, node, (0, 0, 0), lmin, lmax)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    hqq = H[0, 0] * tau + omega
+    mu = O.moments(prob, lmin, lmax, nodes=[node], node_m=[(0, 0, 0)], K=200)
+    s, _ = O.entropy(mu, lf, kT, lmin, lmax)
+    ref = -2.0 * _entropy_integrand(np.array([hqq]), lf, kT)[0]
+    assert abs(s[0] - ref) < 1e-12 and ref > 0
+
+
+def test_entropy_converges_to_eigendecomposition():
+    """s^q -> -2 sum_i U_qi^2 s(lambda_i) on a dense node Hamiltonian; s^q > 0."""
+    prob = synth.small_problem(14, n=(7, 7, 7), rcut=(2, 2, 2), n_atoms=2, rc=1.2)
+    lmin, lmax = _bounds(prob)
+    kT, lf = 1.0, 0.5 * (lmin + lmax) - 0.25 * (lmax - lmin)
+    H, dims, ctr = O.node_dense(prob, 100, (2, 2, 2), lmin, lmax)
+    lam, U = np.linalg.eigh(H)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    exact = -2.0 * np.sum(U[ctr] ** 2 * _entropy_integrand(lam * tau + omega, lf, kT))
+    mu = O.moments(prob, lmin, lmax, nodes=[100], node_m=[(2, 2, 2)], K=200)
+    s, _ = O.entropy(mu, lf, kT, lmin, lmax)
+    assert exact > 0
+    assert abs(s[0] - exact) < 1e-11
+
+
+# --------------------------------------------------------------------------- #
 # Fermi level, Eq. (Ne)
 # --------------------------------------------------------------------------- #
 def test_fermi_level_hits_electron_count_and_brute_force_scan():
