@@ -171,6 +171,20 @@ sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t m
                          double *lambda_f, double *rho, double *u, double *totals,
                          void *stream);
 
+/* Electronic entropy, Eq. (sq), and the band part of the free energy, from the
+ * moments of the last sq_density at the Fermi level of the last
+ * sq_fermi_level:
+ *   s^q = -2 int s(lambda) dmu_q,  s = g log g + (1 - g) log(1 - g),
+ * evaluated like rho^q with the Chebyshev coefficients of s (Eq.
+ * (ChebyshevWeights)); s^q is in units of k_B and is >= 0 up to the
+ * quadrature error.  The paper's free-energy expression writes the entropy
+ * term as -2 theta s^q with s^q already carrying -2 k_B; this library takes
+ * the band free energy as sum_q (u^q - kT s^q).
+ *   s       device [n_nodes] FP64 output, or NULL.
+ *   totals  device [2] FP64 output {S = sum_q s^q, U - kT S}, or NULL.
+ * Requires sq_density and sq_fermi_level on the same context before it. */
+sq_status sq_entropy(sq_ctx *ctx, double *s, double *totals, void *stream);
+
 /* Adjoint (reverse mode) of the forward pass at fixed lambda_f, omega, tau:
  * for y = sum_q (g_rho[q] rho^q + g_u[q] u^q) accumulates
  *   dV[x] += dy/dV(x)          (V's grid, FP64)

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "SQ_OK", -1: "SQ_ERR_ARG", -2: "SQ_ERR_HIP", -3: "SQ_ERR_OOM"
 
 # every entry point declared in include/sq.h
 EXPORTS = ("sq_setup", "sq_destroy", "sq_last_error", "sq_get_info", "sq_density",
-           "sq_fermi_level", "sq_density_backward", "sq_device_status")
+           "sq_fermi_level", "sq_entropy", "sq_density_backward", "sq_device_status")
 
 
 class sq_params(C.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.sq_density.restype = C.c_int
         L.sq_fermi_level.argtypes = [VP, D, D, I32, VP, VP, VP, VP, VP]
         L.sq_fermi_level.restype = C.c_int
+        L.sq_entropy.argtypes = [VP, VP, VP, VP]
+        L.sq_entropy.restype = C.c_int
         L.sq_density_backward.argtypes = [VP, VP, VP, VP, VP, VP]
         L.sq_density_backward.restype = C.c_int
         L.sq_device_status.argtypes = [VP]
@@ -119,6 +121,10 @@ def sq_fermi_level(ctx, Ne_target, tol_Ne, max_iter, lambda_f_ptr, rho_ptr, u_pt
                    stream):
     return check(lib().sq_fermi_level(ctx, Ne_target, tol_Ne, max_iter, lambda_f_ptr, rho_ptr,
                                       u_ptr, totals_ptr, stream))
+
+
+def sq_entropy(ctx, s_ptr, totals_ptr, stream):
+    return check(lib().sq_entropy(ctx, s_ptr, totals_ptr, stream))
 
 
 def sq_density_backward(ctx, g_rho_ptr, g_u_ptr, dV_ptr, dR_ptr, stream):

@@ -702,6 +702,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     ALLOC(c.fw.dp, K1);
     ALLOC(c.fw.dcp, K1);
     ALLOC(c.fw.dup, K1);
+    ALLOC(c.fw.ep, K1);
     c.fw.n_partial = N_PARTIAL;
     c.fw.nq_cap_log2 = NQ_CAP_LOG2;
     if (hipMemset(c.fw.ticket, 0, sizeof(int)) != hipSuccess ||
@@ -870,6 +871,18 @@ sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t m
     HIP_TRY(k_totals(c.fw, c.d_M, c.K, c.d_scal, totals, lambda_f, st));
     if (rho || u) HIP_TRY(k_contract(c.mu_last, c.n_nodes, c.K, c.fw.cp, c.fw.dp, rho, u, st));
     c.have_fermi = true;
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_entropy(sq_ctx *ctx, double *s, double *totals, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    sq_ctx &c = *ctx;
+    if (!c.have_fermi)
+        return fail(SQ_ERR_STATE, "sq_entropy needs sq_density and sq_fermi_level first");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(k_entropy(c.fw, c.d_M, c.K, c.p.kT, c.d_scal, totals, st));
+    if (s) HIP_TRY(k_contract(c.mu_last, c.n_nodes, c.K, c.fw.ep, c.fw.ep, s, nullptr, st));
     c.last_stream = st;
     return SQ_OK;
 }

@@ -41,6 +41,7 @@ struct FermiWork {
     double *partial;            // [n_partial]
     int *ticket;
     double *cp, *dp, *dcp, *dup;  // [K+1] primed coefficients
+    double *ep;                 // [K+1] primed entropy coefficients, negated
     int n_partial;
     int nq_cap_log2;
 };
@@ -58,6 +59,8 @@ hipError_t k_fermi(const FermiWork &f, Scalars *s, const double *M, int K, doubl
                    double tol, int max_iter, const double *lf_in, hipStream_t st);
 hipError_t k_totals(const FermiWork &f, const double *M, int K, const Scalars *s, double *totals,
                     double *lf_out, hipStream_t st);
+hipError_t k_entropy(const FermiWork &f, const double *M, int K, double kT, const Scalars *s,
+                     double *totals, hipStream_t st);
 hipError_t k_contract(const double *mu, int64_t n, int K, const double *cp, const double *dp,
                       double *rho, double *u, hipStream_t st);
 

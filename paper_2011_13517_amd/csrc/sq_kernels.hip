@@ -461,6 +461,39 @@ __global__ void totals_kernel(const double *M, int K, const double *cp, const do
     if (lf_out) *lf_out = s->lambda_f;
 }
 
+// Entropy, Eq. (sq): coefficients of g log g + (1 - g) log(1 - g) at the
+// solved Fermi level, primed and negated, so that contracting the moments
+// with them (2 sum'_k e_k mu_k) gives s^q = -2 int s dmu_q (units of k_B).
+// With t = |x - lf| / th the integrand is -(t e^-t / (1 + e^-t) + log(1 + e^-t)).
+__global__ void entropy_coeff_kernel(const Scalars *s, double kT, int K, double *ep) {
+    __shared__ double sh[16];
+    const int k = blockIdx.x;
+    const double tau = s->tau, om = s->omega;
+    const double lf = (s->lambda_f - om) / tau, th = kT / tau;
+    const int64_t N = 1LL << s->nq_log2;
+    double a = 0.0;
+    for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
+        const double x = cos(M_PI * ((double)j + 0.5) / (double)N);
+        const double t = fabs(x - lf) / th, e = exp(-t);
+        a += (t * e / (1.0 + e) + log1p(e)) * cos_ktj(k, j, N);   // minus the integrand
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) ep[k] = a * (2.0 / (double)N) * (k == 0 ? 0.5 : 1.0);
+}
+
+// S = sum_q s^q = 2 sum'_k e_k M_k and the band free energy U - kT S
+__global__ void entropy_totals_kernel(const double *M, int K, const double *ep, const double *dp,
+                                      double kT, double *totals) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double S = 0.0, U = 0.0;
+    for (int k = 0; k <= K; ++k) {
+        S += ep[k] * M[k];
+        U += dp[k] * M[k];
+    }
+    totals[0] = 2.0 * S;
+    totals[1] = 2.0 * U - kT * 2.0 * S;
+}
+
 // rho^q = 2 sum'_k c_k mu_k^q, u^q = 2 sum'_k d_k mu_k^q  (one wave per node)
 __global__ void contract_kernel(const double *mu, int64_t n, int K, const double *cp,
                                 const double *dp, double *rho, double *u) {
@@ -574,6 +607,15 @@ hipError_t k_totals(const FermiWork &f, const double *M, int K, const Scalars *s
                     double *lf_out, hipStream_t st) {
     hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, st, M, K, f.cp, f.dp, f.dcp, f.dup, s,
                        totals, lf_out);
+    return hipGetLastError();
+}
+
+hipError_t k_entropy(const FermiWork &f, const double *M, int K, double kT, const Scalars *s,
+                     double *totals, hipStream_t st) {
+    hipLaunchKernelGGL(entropy_coeff_kernel, dim3(K + 1), dim3(256), 0, st, s, kT, K, f.ep);
+    if (totals)
+        hipLaunchKernelGGL(entropy_totals_kernel, dim3(1), dim3(64), 0, st, M, K, f.ep, f.dp, kT,
+                           totals);
     return hipGetLastError();
 }
 

@@ -124,6 +124,17 @@ class Context:
                          _ptr(rho), _ptr(u), _ptr(totals), _stream())
         return lambda_f, rho, u, totals
 
+    def entropy(self, s: Optional[torch.Tensor] = None, totals: Optional[torch.Tensor] = None,
+                device=None):
+        """sq_entropy: pointwise entropy s^q (units of k_B) and {S, U - kT S}."""
+        dev = device or torch.device("cuda")
+        if s is None:
+            s = torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+        if totals is None:
+            totals = torch.empty(2, dtype=torch.float64, device=dev)
+        L.sq_entropy(self.ctx, _ptr(s), _ptr(totals), _stream())
+        return s, totals
+
     def backward(self, g_rho: Optional[torch.Tensor], g_u: Optional[torch.Tensor],
                  dV: Optional[torch.Tensor] = None, dR: Optional[torch.Tensor] = None):
         """sq_density_backward: accumulates into dV (V grid) and dR [n_atoms, 3]."""
