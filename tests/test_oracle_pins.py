@@ -434,6 +434,60 @@ def test_entropy_converges_to_eigendecomposition():
 
 
 # --------------------------------------------------------------------------- #
+# Gauss quadrature of the local spectral measure (LSSGQ), Eq. (Lanczos)
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET, synth.BC_EMBEDDED])
+def test_gauss_rule_exact_to_degree_2K_minus_1(bc):
+    """A K-point Gauss rule integrates T_j exactly for j <= 2K-1: against the
+    Chebyshev moments of the three-term recurrence (an independent route)."""
+    prob = synth.small_problem(31 + bc, n=(9, 8, 10), bc=bc, rcut=(2, 2, 3), n_atoms=3, rc=1.3)
+    lmin, lmax = _bounds(prob)
+    nodes = [0, 17, 200, 555, 719]
+    K = 7
+    lam, w = O.gauss_rules(prob, lmin, lmax, K, nodes=nodes)
+    mu = O.moments(prob, lmin, lmax, nodes=nodes, K=2 * K + 2)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    th = (lam - omega) / tau
+    for j in range(2 * K):
+        np.testing.assert_allclose(np.sum(w * _tk(j, th), axis=1), mu[:, j], rtol=0, atol=1e-12)
+    # degree 2K is not integrated exactly: the pin above is sharp
+    assert np.abs(np.sum(w * _tk(2 * K, th), axis=1) - mu[:, 2 * K]).max() > 1e-8
+
+
+def test_gauss_rule_closed_krylov_space_is_the_spectral_measure():
+    """K beyond the region size: the rule is the exact spectral measure of e_q,
+    so sum_k w_k f(lambda_k) = sum_i U_qi^2 f(lambda_i) for any f (dense eigh)."""
+    prob = synth.small_problem(14, n=(7, 7, 7), rcut=(1, 1, 1), n_atoms=2, rc=1.2)
+    lmin, lmax = _bounds(prob)
+    H, dims, ctr = O.node_dense(prob, 100, (1, 1, 1), lmin, lmax)
+    ev, U = np.linalg.eigh(H)
+    omega, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    lam, w = O.gauss_rules(prob, lmin, lmax, 40, nodes=[100])
+    kT, lf = 0.4, omega - 0.2 * tau
+    rho, u, s_ = O.gauss_fields(lam, w, lf, kT)
+    g = 1.0 / (1.0 + np.exp((ev * tau + omega - lf) / kT))
+    assert abs(rho[0] - 2.0 * np.sum(U[ctr] ** 2 * g)) < 1e-12
+    assert abs(u[0] - 2.0 * np.sum(U[ctr] ** 2 * (ev * tau + omega) * g)) < 1e-11
+    assert abs(np.sum(w) - 1.0) < 1e-13
+
+
+def test_gauss_fermi_level_hits_count_and_scan():
+    prob = synth.small_problem(41, n=(8, 8, 8), rcut=(2, 2, 2), n_atoms=3, rc=1.3)
+    lmin, lmax = _bounds(prob)
+    lam, w = O.gauss_rules(prob, lmin, lmax, 10, nodes=np.arange(0, 512, 3))
+    kT = 0.2
+    Ne = 0.4 * 2 * lam.shape[0]
+    lf, it = O.gauss_fermi_level(lam, w, kT, lmin, lmax, Ne, tol=1e-10)
+    rho, _, _ = O.gauss_fields(lam, w, lf, kT)
+    assert abs(rho.sum() - Ne) < 1e-9
+    # brute-force scan brackets the root
+    xs = np.linspace(lmin, lmax, 2001)
+    ns = np.array([O.gauss_fields(lam, w, x, kT)[0].sum() for x in xs])
+    i = np.searchsorted(ns, Ne)
+    assert xs[i - 1] <= lf <= xs[i]
+
+
+# --------------------------------------------------------------------------- #
 # Fermi level, Eq. (Ne)
 # --------------------------------------------------------------------------- #
 def test_fermi_level_hits_electron_count_and_brute_force_scan():
