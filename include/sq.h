@@ -199,6 +199,50 @@ sq_status sq_entropy(sq_ctx *ctx, double *s, double *totals, void *stream);
 sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_u, double *dV,
                               double *dR, void *stream);
 
+/* Spectral Gauss quadrature (LSSGQ), Section 2.2: K-point Gauss rule of the
+ * local spectral measure of every node from K steps of Eq. (Lanczos) on the
+ * node Hamiltonian (K = params.order), started at e_q without
+ * reorthogonalisation.  The rule's nodes are the eigenvalues of the node's
+ * K x K Jacobi matrix (lambda = tau theta + omega) and its weights the squared
+ * first components of the normalised eigenvectors (the paper's text swaps the
+ * two symbols; this is the Golub-Welsch reading).  A Krylov space that closes
+ * before K steps (b_{k+1} <= 1e-14) gives the shorter exact rule: the last
+ * node is repeated and its extra weights are 0.  The Lanczos vectors run in
+ * params.precision; a_k, b_k and the eigensolve are FP64.
+ *   V            device, FP64, the local potential on V's grid (read only).
+ *   lambda_min,
+ *   lambda_max   scaling bounds as in sq_density (NaN, NaN: device estimate).
+ *   nodes,
+ *   weights      device [n_nodes][K] FP64 outputs, both given or both NULL
+ *                (kept internally); they hold the rules that
+ *                sq_gauss_fermi_level reads, so caller buffers must stay valid
+ *                until then.  Nodes of a row ascend.
+ * The first call with NULL outputs allocates 2 n_nodes K doubles, and every
+ * context's first call a small partial-sum buffer; later calls allocate
+ * nothing.  Invalidates the state of sq_density / sq_fermi_level (both share
+ * the scaling), so sq_entropy and sq_density_backward need a new sq_density.
+ * Eigensolve failures (none expected) show in sq_device_status as
+ * SQ_ERR_NOT_CONVERGED. */
+sq_status sq_gauss_density(sq_ctx *ctx, const double *V, double lambda_min, double lambda_max,
+                           double *nodes, double *weights, void *stream);
+
+/* Fermi level and pointwise fields from the Gauss rules of the last
+ * sq_gauss_density, Eqs. (Ne), (rhoq), (uq), (sq):
+ *   N_e = 2 sum_q sum_k w_k g(lambda_k),   rho^q = 2 sum_k w_k g(lambda_k),
+ *   u^q = 2 sum_k w_k lambda_k g(lambda_k),
+ *   s^q = -2 sum_k w_k (g log g + (1 - g) log(1 - g))  (units of k_B),
+ * g = 1 / (1 + exp((lambda - lambda_f) / kT)).  Bisection as in
+ * sq_fermi_level, except that lambda_f is the last midpoint evaluated on
+ * every stop.  max_iter == 0 uses *lambda_f as given.
+ *   lambda_f       device scalar FP64: output (input when max_iter == 0).
+ *   rho, u, s      device [n_nodes] FP64 outputs, or NULL.
+ *   totals         device [8] FP64 output: {N_e, U, S, U - kT S, omega, tau,
+ *                  iterations, status}, or NULL.
+ * Requires a preceding sq_gauss_density on the same context. */
+sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
+                               double *lambda_f, double *rho, double *u, double *s,
+                               double *totals, void *stream);
+
 /* Synchronises the context's last stream and returns the device-side status
  * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */
 sq_status sq_device_status(sq_ctx *ctx);

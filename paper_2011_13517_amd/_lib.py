@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "SQ_OK", -1: "SQ_ERR_ARG", -2: "SQ_ERR_HIP", -3: "SQ_ERR_OOM"
 
 # every entry point declared in include/sq.h
 EXPORTS = ("sq_setup", "sq_destroy", "sq_last_error", "sq_get_info", "sq_density",
-           "sq_fermi_level", "sq_entropy", "sq_density_backward", "sq_device_status")
+           "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level",
+           "sq_density_backward", "sq_device_status")
 
 
 class sq_params(C.Structure):
@@ -77,6 +78,10 @@ def lib():
         L.sq_fermi_level.restype = C.c_int
         L.sq_entropy.argtypes = [VP, VP, VP, VP]
         L.sq_entropy.restype = C.c_int
+        L.sq_gauss_density.argtypes = [VP, VP, D, D, VP, VP, VP]
+        L.sq_gauss_density.restype = C.c_int
+        L.sq_gauss_fermi_level.argtypes = [VP, D, D, I32, VP, VP, VP, VP, VP, VP]
+        L.sq_gauss_fermi_level.restype = C.c_int
         L.sq_density_backward.argtypes = [VP, VP, VP, VP, VP, VP]
         L.sq_density_backward.restype = C.c_int
         L.sq_device_status.argtypes = [VP]
@@ -125,6 +130,16 @@ def sq_fermi_level(ctx, Ne_target, tol_Ne, max_iter, lambda_f_ptr, rho_ptr, u_pt
 
 def sq_entropy(ctx, s_ptr, totals_ptr, stream):
     return check(lib().sq_entropy(ctx, s_ptr, totals_ptr, stream))
+
+
+def sq_gauss_density(ctx, V_ptr, lmin, lmax, nodes_ptr, weights_ptr, stream):
+    return check(lib().sq_gauss_density(ctx, V_ptr, lmin, lmax, nodes_ptr, weights_ptr, stream))
+
+
+def sq_gauss_fermi_level(ctx, Ne, tol, max_iter, lf_ptr, rho_ptr, u_ptr, s_ptr, totals_ptr,
+                         stream):
+    return check(lib().sq_gauss_fermi_level(ctx, Ne, tol, max_iter, lf_ptr, rho_ptr, u_ptr,
+                                            s_ptr, totals_ptr, stream))
 
 
 def sq_density_backward(ctx, g_rho_ptr, g_u_ptr, dV_ptr, dR_ptr, stream):

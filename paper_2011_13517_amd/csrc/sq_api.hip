@@ -67,6 +67,7 @@ struct Group {
     bool maskz = false;
     int begin = 0, count = 0;
     int grid_fwd = 1, grid_adj = 1;
+    int grid_gauss = 0;   // set on the first Gauss sweep
 };
 enum { PLAN_MERGED = 0, PLAN_SPLIT = 1 };
 
@@ -156,6 +157,11 @@ struct sq_ctx {
     int64_t ckpt_stride = 0;
     void *d_ckpt = nullptr;
     bool have_density = false, have_fermi = false;
+    // Gauss quadrature: rules of the last sq_gauss_density (caller's buffers
+    // or the internal ones, allocated on first use) and field partials
+    double *d_glam = nullptr, *d_gwgt = nullptr, *d_gpart = nullptr;
+    double *glam_last = nullptr, *gwgt_last = nullptr;
+    bool have_gauss = false;
     hipStream_t last_stream = nullptr;
 
     template <typename T>
@@ -383,6 +389,44 @@ sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
     c.plan = best_plan;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best_plan;
+    return SQ_OK;
+}
+
+// spectral bounds (given, or both NaN: device Lanczos estimate) and the
+// scaled diagonal of V
+sq_status prepare_operator(sq_ctx &c, const double *V, double lambda_min, double lambda_max,
+                           hipStream_t st) {
+    const bool estimate = std::isnan(lambda_min) && std::isnan(lambda_max);
+    if (!estimate && !(lambda_max > lambda_min && std::isfinite(lambda_min) &&
+                       std::isfinite(lambda_max)))
+        return fail(SQ_ERR_SPECTRUM, "need lambda_max > lambda_min (or both NaN)");
+    if (estimate) {
+        FullOp op{};
+        for (int a = 0; a < 3; ++a) {
+            op.N[a] = c.N[a];
+            op.ih2[a] = c.ih2[a];
+        }
+        op.periodic = c.periodic;
+        op.r = c.r;
+        for (int p = 0; p <= MAX_R; ++p) op.w[p] = c.w[p];
+        op.kin = c.kin;
+        op.h3 = c.h3;
+        op.V = V;
+        op.n_atoms = c.n_atoms;
+        op.sup_off = c.d_sup_off;
+        op.sup_idx = c.d_sup_idx;
+        op.chi = c.d_chi_full;
+        op.cJ = c.d_cJ;
+        op.n_upts = c.n_upts;
+        op.pt_idx = c.d_pt_idx;
+        op.pt_off = c.d_pt_off;
+        op.pt_row = c.d_pt_row;
+        op.pt_atom = c.d_pt_atom;
+        HIP_TRY(k_lanczos_bounds(op, c.lz, LANCZOS_STEPS, LANCZOS_SEED, LANCZOS_MARGIN, c.d_scal, st));
+    } else {
+        HIP_TRY(k_set_bounds(c.d_scal, lambda_min, lambda_max, st));
+    }
+    HIP_TRY(k_build_diag(V, c.nv, c.kin, c.d_scal, c.d_D64, c.d_D32, st));
     return SQ_OK;
 }
 
@@ -816,37 +860,7 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
     if (!V) return fail(SQ_ERR_ARG, "V is NULL");
     sq_ctx &c = *ctx;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool estimate = std::isnan(lambda_min) && std::isnan(lambda_max);
-    if (!estimate && !(lambda_max > lambda_min && std::isfinite(lambda_min) &&
-                       std::isfinite(lambda_max)))
-        return fail(SQ_ERR_SPECTRUM, "need lambda_max > lambda_min (or both NaN)");
-    if (estimate) {
-        FullOp op{};
-        for (int a = 0; a < 3; ++a) {
-            op.N[a] = c.N[a];
-            op.ih2[a] = c.ih2[a];
-        }
-        op.periodic = c.periodic;
-        op.r = c.r;
-        for (int p = 0; p <= MAX_R; ++p) op.w[p] = c.w[p];
-        op.kin = c.kin;
-        op.h3 = c.h3;
-        op.V = V;
-        op.n_atoms = c.n_atoms;
-        op.sup_off = c.d_sup_off;
-        op.sup_idx = c.d_sup_idx;
-        op.chi = c.d_chi_full;
-        op.cJ = c.d_cJ;
-        op.n_upts = c.n_upts;
-        op.pt_idx = c.d_pt_idx;
-        op.pt_off = c.d_pt_off;
-        op.pt_row = c.d_pt_row;
-        op.pt_atom = c.d_pt_atom;
-        HIP_TRY(k_lanczos_bounds(op, c.lz, LANCZOS_STEPS, LANCZOS_SEED, LANCZOS_MARGIN, c.d_scal, st));
-    } else {
-        HIP_TRY(k_set_bounds(c.d_scal, lambda_min, lambda_max, st));
-    }
-    HIP_TRY(k_build_diag(V, c.nv, c.kin, c.d_scal, c.d_D64, c.d_D32, st));
+    TRY(prepare_operator(c, V, lambda_min, lambda_max, st));
     HIP_TRY(k_fill_i32(c.d_status, 0, 1, st));
     double *mu = moments ? moments : c.d_mu;
     TRY(run_forward(c, c.groups, c.d_items, mu, st));
@@ -854,6 +868,7 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
     c.mu_last = mu;
     c.have_density = true;
     c.have_fermi = false;
+    c.have_gauss = false;
     c.last_stream = st;
     return SQ_OK;
 }
@@ -932,6 +947,81 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
     return SQ_OK;
 }
 
+sq_status sq_gauss_density(sq_ctx *ctx, const double *V, double lambda_min, double lambda_max,
+                           double *nodes, double *weights, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    if (!V) return fail(SQ_ERR_ARG, "V is NULL");
+    if ((nodes == nullptr) != (weights == nullptr))
+        return fail(SQ_ERR_ARG, "nodes and weights must both be given or both be NULL");
+    sq_ctx &c = *ctx;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t nk = (size_t)c.n_nodes * (size_t)c.K;
+    if (!c.d_gpart) TRY(c.alloc(&c.d_gpart, 3 * (size_t)N_PARTIAL));
+    if (!nodes && !c.d_glam) {
+        TRY(c.alloc(&c.d_glam, nk));
+        TRY(c.alloc(&c.d_gwgt, nk));
+    }
+    double *L = nodes ? nodes : c.d_glam, *W = nodes ? weights : c.d_gwgt;
+    int ncu = 0;
+    for (Group &g : c.groups) {
+        if (g.grid_gauss) continue;
+        if (!ncu) {
+            int dev = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        }
+        const int occ = gauss_lanczos_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
+        g.grid_gauss = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+    }
+    TRY(prepare_operator(c, V, lambda_min, lambda_max, st));
+    HIP_TRY(k_fill_i32(c.d_status, 0, 1, st));
+    HIP_TRY(k_fill_i32(c.d_counter, 0, (int64_t)c.groups.size(), st));
+    auto sweep = [&](auto tag) -> sq_status {
+        using T = decltype(tag);
+        for (size_t g = 0; g < c.groups.size(); ++g) {
+            RegionArgs<T> a{};
+            fill_region_args(c, a);
+            a.items = c.d_items + c.groups[g].begin;
+            a.n_items = c.groups[g].count;
+            a.counter = c.d_counter + g;
+            a.moments = nullptr;
+            HIP_TRY(launch_gauss_lanczos(c.prec, c.groups[g].E, c.r, c.groups[g].maskz, &a, L, W,
+                                         c.groups[g].grid_gauss, st));
+        }
+        return SQ_OK;
+    };
+    if (c.prec == SQ_FP64) TRY(sweep(double{}));
+    else TRY(sweep(float{}));
+    HIP_TRY(k_gauss_eig(L, W, c.n_nodes, c.K, c.d_scal, c.d_status, st));
+    c.glam_last = L;
+    c.gwgt_last = W;
+    c.have_gauss = true;
+    c.have_density = false;
+    c.have_fermi = false;
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
+                               double *lambda_f, double *rho, double *u, double *s,
+                               double *totals, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    sq_ctx &c = *ctx;
+    if (!c.have_gauss)
+        return fail(SQ_ERR_STATE, "sq_gauss_fermi_level needs a preceding sq_gauss_density");
+    if (!lambda_f) return fail(SQ_ERR_ARG, "lambda_f is NULL");
+    if (max_iter < 0 || max_iter > 100000) return fail(SQ_ERR_ARG, "max_iter out of range");
+    if (max_iter > 0 && !(tol_Ne >= 0.0)) return fail(SQ_ERR_ARG, "tol_Ne must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nk = c.n_nodes * (int64_t)c.K;
+    HIP_TRY(k_gauss_fermi(c.fw, c.d_scal, c.glam_last, c.gwgt_last, nk, c.p.kT, Ne_target, tol_Ne,
+                          max_iter, lambda_f, st));
+    HIP_TRY(k_gauss_fields(c.glam_last, c.gwgt_last, c.n_nodes, c.K, c.p.kT, c.d_scal, rho, u, s,
+                           c.d_gpart, N_PARTIAL, totals, lambda_f, st));
+    c.last_stream = st;
+    return SQ_OK;
+}
+
 sq_status sq_device_status(sq_ctx *ctx) {
     if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(ctx->last_stream));
@@ -939,6 +1029,7 @@ sq_status sq_device_status(sq_ctx *ctx) {
     Scalars s{};
     HIP_TRY(hipMemcpy(&flag, ctx->d_status, sizeof(flag), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&s, ctx->d_scal, sizeof(s), hipMemcpyDeviceToHost));
+    if (flag & 4) return fail(SQ_ERR_NOT_CONVERGED, "a Jacobi-matrix eigensolve did not converge");
     if (flag) return fail(SQ_ERR_ARG, "a region touched more atoms than the kernel's atom table holds");
     if (s.status) return fail((sq_status)s.status, "device reported status %d", s.status);
     return SQ_OK;

@@ -117,6 +117,10 @@ struct AdjointArgs {
 hipError_t launch_forward(int prec, int E, int R, bool maskz, const void *args, int grid,
                           hipStream_t s);
 int forward_blocks_per_cu(int prec, int E, int R, bool maskz);
+// Lanczos sweep of the Gauss quadrature: alpha, beta [n_nodes][K] (FP64)
+hipError_t launch_gauss_lanczos(int prec, int E, int R, bool maskz, const void *args,
+                                double *alpha, double *beta, int grid, hipStream_t s);
+int gauss_lanczos_blocks_per_cu(int prec, int E, int R, bool maskz);
 // storeall: the forward pass keeps every v_k (checkpoint stride 1) instead
 // of checkpoints every ckpt_every steps plus the reverse rebuild.
 hipError_t launch_adjoint(int prec, int E, int R, bool storeall, bool grad, const void *args,

@@ -64,4 +64,17 @@ hipError_t k_entropy(const FermiWork &f, const double *M, int K, double kT, cons
 hipError_t k_contract(const double *mu, int64_t n, int K, const double *cp, const double *dp,
                       double *rho, double *u, hipStream_t st);
 
+// Gauss quadrature (LSSGQ): per-node eigensolve of the Jacobi matrices held in
+// (lam, wgt) in place, the Fermi-level bisection over the rules, and the
+// pointwise fields with their totals {N_e, U, S, U - kT S, omega, tau, iters,
+// status}.
+hipError_t k_gauss_eig(double *lam, double *wgt, int64_t n, int K, const Scalars *s,
+                       int32_t *status, hipStream_t st);
+hipError_t k_gauss_fermi(const FermiWork &f, Scalars *s, const double *lam, const double *wgt,
+                         int64_t nk, double kT, double Ne, double tol, int max_iter,
+                         const double *lf_in, hipStream_t st);
+hipError_t k_gauss_fields(const double *lam, const double *wgt, int64_t n, int K, double kT,
+                          const Scalars *s, double *rho, double *u, double *sq, double *partial,
+                          int n_partial, double *totals, double *lf_out, hipStream_t st);
+
 }  // namespace sqk

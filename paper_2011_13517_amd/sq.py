@@ -135,6 +135,40 @@ class Context:
         L.sq_entropy(self.ctx, _ptr(s), _ptr(totals), _stream())
         return s, totals
 
+    # -- Gauss quadrature (LSSGQ) ---------------------------------------------
+    def gauss_density(self, V: torch.Tensor, lambda_min: float = math.nan,
+                      lambda_max: float = math.nan, nodes: Optional[torch.Tensor] = None,
+                      weights: Optional[torch.Tensor] = None):
+        """sq_gauss_density: Gauss nodes and weights [n_nodes, K] (FP64, device)."""
+        _dev(V)
+        dev = V.device
+        if nodes is None:
+            nodes = torch.empty((self.n_nodes, self.K), dtype=torch.float64, device=dev)
+        if weights is None:
+            weights = torch.empty((self.n_nodes, self.K), dtype=torch.float64, device=dev)
+        L.sq_gauss_density(self.ctx, _ptr(V), float(lambda_min), float(lambda_max), _ptr(nodes),
+                           _ptr(weights), _stream())
+        # sq_gauss_fermi_level reads these rules later: keep them alive
+        self._rules = (nodes, weights)
+        return nodes, weights
+
+    def gauss_fermi_level(self, Ne: float = 0.0, tol: float = 1e-10, max_iter: int = 200,
+                          lambda_f: Optional[torch.Tensor] = None, want_fields: bool = True,
+                          device=None):
+        """sq_gauss_fermi_level: (lambda_f[1], rho[n], u[n], s[n], totals[8]) with
+        totals = {N_e, U, S, U - kT S, omega, tau, iterations, status}."""
+        dev = device or torch.device("cuda")
+        if lambda_f is None:
+            lambda_f = torch.zeros(1, dtype=torch.float64, device=dev)
+        rho = u = s = None
+        if want_fields:
+            rho, u, s = (torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+                         for _ in range(3))
+        totals = torch.empty(8, dtype=torch.float64, device=dev)
+        L.sq_gauss_fermi_level(self.ctx, float(Ne), float(tol), int(max_iter), _ptr(lambda_f),
+                               _ptr(rho), _ptr(u), _ptr(s), _ptr(totals), _stream())
+        return lambda_f, rho, u, s, totals
+
     def backward(self, g_rho: Optional[torch.Tensor], g_u: Optional[torch.Tensor],
                  dV: Optional[torch.Tensor] = None, dR: Optional[torch.Tensor] = None):
         """sq_density_backward: accumulates into dV (V grid) and dR [n_atoms, 3]."""
