@@ -32,16 +32,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# sources the profiled kernels are compiled from (the host-side API and the
+# support kernels do not change what the region kernels fetch and write)
+KERNEL_SOURCES = ("sq_internal.h", "sq_region.h", "sq_forward.hip", "sq_adjoint_kernel.h",
+                  "sq_adjoint.hip", "sq_adjoint_r1.hip", "sq_adjoint_r2.hip", "sq_adjoint_r3.hip",
+                  "sq_adjoint_r4.hip", "sq_adjoint_r5.hip", "sq_adjoint_r6.hip",
+                  "sq_gauss_lanczos.hip", "sq_gauss.hip")
+
+
 def kernel_source_hash():
-    """sha256 over the HIP sources of the library (names and contents)."""
+    """sha256 over the HIP sources of the profiled kernels (names and contents)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2011_13517_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".h", ".hip")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
@@ -63,6 +70,60 @@ def recorded_traffic(kernel):
             "bytes": k["fetch_bytes"] + k["write_bytes"], "source": os.path.basename(path)}
 
 
+def gauss_leg(ctx, prob, V, tot, f_app, region_points, dev):
+    """Gauss-quadrature density on the same workload and context: K Lanczos
+    steps per node (sq_gauss_density: bounds as in the Chebyshev run, the
+    Lanczos sweep, the Jacobi eigensolves) and sq_gauss_fermi_level (bisection
+    and rho, u, s), timed with HIP events on the current stream; fields of a
+    few nodes against the oracle's rules at the same lambda_f."""
+    import torch
+
+    import oracle as O
+    K, n = ctx.K, ctx.n_nodes
+    om, tau = float(tot[4]), float(tot[5])
+    lmin, lmax = om - tau, om + tau
+    nodes = torch.empty((n, K), dtype=torch.float64, device=dev)
+    wts = torch.empty_like(nodes)
+    Ne = prob.Ne if prob.Ne is not None else 0.0
+    ctx.gauss_density(V, lmin, lmax, nodes=nodes, weights=wts)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    ctx.gauss_density(V, lmin, lmax, nodes=nodes, weights=wts)
+    e[1].record()
+    lf, rho, u, s, gt = ctx.gauss_fermi_level(Ne=Ne, tol=1e-8, max_iter=200, device=dev)
+    e[2].record()
+    torch.cuda.synchronize()
+    ctx.status()
+    t_rules = e[0].elapsed_time(e[1]) * 1e-3
+    t_fields = e[1].elapsed_time(e[2]) * 1e-3
+    gt = gt.cpu().numpy()
+    log(f"Gauss quadrature: rules {t_rules:.3f} s, Fermi level + fields {t_fields:.3f} s, "
+        f"N_e={gt[0]:.10f} lambda_f={lf.item():.10f}")
+    rng = np.random.default_rng(13)
+    sample = np.sort(rng.choice(n, 4, replace=False))
+    lam_o, w_o = O.gauss_rules(prob, lmin, lmax, K, nodes=prob.node_list()[sample])
+    rho_o, u_o, s_o = O.gauss_fields(lam_o, w_o, lf.item(), prob.kT)
+    rho_g = rho.cpu().numpy()
+    achieved = region_points * K * f_app / t_rules / 1e12
+    return {
+        "metric": "node-Lanczos-steps/s",
+        "value": n * K / (t_rules + t_fields),
+        "seconds": {"rules": t_rules, "fermi_fields": t_fields},
+        "roofline": dict(bound="alu", kernel="gauss_lanczos_kernel + gauss_eig_kernel",
+                         achieved=achieved, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
+                         frac=achieved / (PEAK_FP32_VALU / 1e12),
+                         traffic=recorded_traffic("gauss_lanczos_kernel")),
+        "totals": {"Ne": float(gt[0]), "U": float(gt[1]), "S": float(gt[2]),
+                   "U_minus_kT_S": float(gt[3]), "lambda_f": float(lf.item())},
+        "accuracy": {"max_abs_drho": float(np.abs(rho_g[sample] - rho_o).max()),
+                     "rel_drho": float(np.abs(rho_g[sample] - rho_o).max() / np.abs(rho_g).max()),
+                     "sample_nodes": int(sample.size),
+                     "reference": "FP64 oracle Gauss rules at the GPU's lambda_f"},
+        "precision": "FP32 Lanczos vectors, FP64 a_k, b_k, eigensolve, bisection, fields",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +132,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-gauss", action="store_true",
+                    help="skip the Gauss-quadrature (LSSGQ) leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (a kernel of "
@@ -182,6 +245,8 @@ def main():
 
     # accuracy against the FP64 oracle on sampled nodes
     extra = {}
+    if not args.no_gauss:
+        extra["lssgq"] = gauss_leg(ctx, prob, V, tot, f_app, region_points, dev)
     rho_np = rho.cpu().numpy()
     tot_om, tot_tau = float(tot[4]), float(tot[5])
     lmin, lmax = tot_om - tot_tau, tot_om + tot_tau
