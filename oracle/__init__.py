@@ -4,10 +4,12 @@ TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` are the only users.  The product library never
 imports, links or runs anything under ``oracle/``.
 
-The arithmetic lives in plain C (``sq_oracle.c``, FP64, one routine per step of
-the method); this module only marshals numpy arrays into it, plus the two steps
-that are plain library calls (the tridiagonal eigenvalues of the Lanczos matrix
-and nothing else).
+The arithmetic of the density path lives in plain C (``sq_oracle.c``, FP64, one
+routine per step of the method); this module marshals numpy arrays into it.
+The Gauss-quadrature rules (Lanczos on top of the C operator, with the
+tridiagonal eigensolve as a library call) and the Clenshaw-Curtis nonlocal
+force (the C operator for the recurrence, numpy for the box gradient and the
+projections) are written here in numpy, FP64.
 """
 from __future__ import annotations
 
@@ -334,6 +336,107 @@ def gauss_fermi_level(lam, wgt, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
         if hi - lo < 4.0 * np.finfo(float).eps * max(abs(lo), abs(hi)):
             break
     return mid, it
+
+
+# --------------------------------------------------------------------------- #
+# Nonlocal force by the Clenshaw-Curtis quadrature, Eq. (NLforceSQ)
+# --------------------------------------------------------------------------- #
+def fd_first_weights(r):
+    """Central first-derivative weights of radius r (Section 3's FD gradient):
+    f'(x) ~ sum_p w_p (f(x + p h) - f(x - p h)) / h with
+    w_p = (-1)^(p+1) (r!)^2 / (p (r-p)! (r+p)!)."""
+    from math import factorial
+    return np.array([0.0] + [(-1.0) ** (p + 1) * factorial(r) ** 2 /
+                             (p * factorial(r - p) * factorial(r + p)) for p in range(1, r + 1)])
+
+
+def _box_grad(gam, dims, h, r, axis):
+    """d/dx_axis of a box function (flattened x fastest) by the radius-r central
+    stencil, with the function taken as zero outside the box."""
+    G = gam.reshape(dims[2], dims[1], dims[0])     # [z][y][x]
+    ax = 2 - axis
+    wp = fd_first_weights(r)
+    out = np.zeros_like(G)
+    n = G.shape[ax]
+    for p in range(1, r + 1):
+        if p >= n:
+            break
+        up = np.zeros_like(G)
+        dn = np.zeros_like(G)
+        sl_dst = [slice(None)] * 3
+        sl_src = [slice(None)] * 3
+        sl_dst[ax], sl_src[ax] = slice(0, n - p), slice(p, n)
+        up[tuple(sl_dst)] = G[tuple(sl_src)]          # f(x + p)
+        sl_dst[ax], sl_src[ax] = slice(p, n), slice(0, n - p)
+        dn[tuple(sl_dst)] = G[tuple(sl_src)]          # f(x - p)
+        out += wp[p] * (up - dn)
+    return (out / h[axis]).reshape(-1)
+
+
+def box_projectors(prob, lo, dims):
+    """{atom: (box indices [m], chi [m, n_proj])} for the atoms whose support meets
+    the box (support points mapped into box coordinates; periodic grids wrap)."""
+    N = prob.vshape
+    out = {}
+    for J in range(prob.n_atoms):
+        s0, s1 = int(prob.sup_off[J]), int(prob.sup_off[J + 1])
+        idx = prob.sup_idx[s0:s1]
+        g = np.stack([idx % N[0], (idx // N[0]) % N[1], idx // (N[0] * N[1])], axis=1)
+        t = g - np.asarray(lo)[None, :]
+        if prob.bc == 0:
+            t = np.mod(t, np.asarray(N)[None, :])
+        inside = np.all((t >= 0) & (t < np.asarray(dims)[None, :]), axis=1)
+        if not inside.any():
+            continue
+        t = t[inside]
+        bi = t[:, 0] + dims[0] * (t[:, 1] + dims[1] * t[:, 2])
+        out[J] = (bi, prob.chi[s0:s1][inside])
+    return out
+
+
+def cc_nonlocal_force(prob, lmin, lmax, lambda_f, nodes=None, node_m=None, V=None):
+    """f_J,nl = -4 sum_q e_q^T V_J^q grad_h (sum'_k c_k v_k^q), Eq. (NLforceSQ) in
+    its discrete form (Section 3), for every atom: [n_atoms, 3].
+
+    v_k^q: Eq. (Chebyshev) on the node's region (the same box and truncated
+    Hamiltonian as the moments); c_k: Eq. (ChebyshevWeights) at lambda_f with
+    c_0 halved; grad_h: the radius-r central stencil on the box with zero
+    outside it; e_q^T V_J^q f = h1 h2 h3 sum_lm c_Jl chi_Jlm(q) (chi_Jlm . f)
+    over the box.  Nodes outside every support contribute nothing."""
+    b = _Bound(prob)
+    Vv = b.V if V is None else np.ascontiguousarray(V, np.float64)
+    nodes, nm, mdef = _nodes_and_widths(prob, nodes, node_m)
+    K = prob.order
+    c, _ = cheb_coeffs(KIND_G, lambda_f, prob.kT, lmin, lmax, K)
+    cp = c.copy()
+    cp[0] *= 0.5
+    h3 = float(np.prod(prob.h))
+    f = np.zeros((prob.n_atoms, 3))
+    for i, q in enumerate(nodes):
+        m = mdef if nm is None else nm[i]
+        lo, dims, ctr3 = node_box(prob, q, m)
+        projs = box_projectors(prob, lo, dims)
+        ctr = int(ctr3[0] + dims[0] * (ctr3[1] + dims[1] * ctr3[2]))
+        at_q = {J: chi[bi == ctr].sum(axis=0) for J, (bi, chi) in projs.items()
+                if np.any(bi == ctr)}
+        if not at_q:
+            continue
+        v0 = np.zeros(int(np.prod(dims)))
+        v0[ctr] = 1.0
+        gam = cp[0] * v0
+        vp, v = v0, apply_node(prob, q, m, lmin, lmax, v0, V=Vv)[2]
+        gam = gam + cp[1] * v
+        for k in range(1, K):
+            vn = 2.0 * apply_node(prob, q, m, lmin, lmax, v, V=Vv)[2] - vp
+            vp, v = v, vn
+            gam = gam + cp[k + 1] * v
+        for a in range(3):
+            dg = _box_grad(gam, dims, prob.h, prob.r, a)
+            for J, chq in at_q.items():
+                bi, chi = projs[J]
+                proj = chi.T @ dg[bi]                      # chi_Jlm . d_a gamma
+                f[J, a] += -4.0 * h3 * np.sum(prob.c[J] * chq * proj)
+    return f
 
 
 def adjoint(prob, lmin, lmax, a, nodes=None, node_m=None, V=None, with_dR=True):

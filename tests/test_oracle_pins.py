@@ -629,3 +629,89 @@ def test_adjoint_dR_central_difference():
                 ys.append(np.sum(a * O.moments(p2, lmin, lmax, nodes=nodes)))
             fd = (ys[0] - ys[1]) / (2 * eps)
             assert abs(fd - dR[J, x]) < 1e-6 * max(1.0, abs(fd)), (J, x, fd, dR[J, x])
+
+
+# --------------------------------------------------------------------------- #
+# Nonlocal force by the Clenshaw-Curtis quadrature, Eq. (NLforceSQ)
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6])
+def test_fd_first_weights_exact_to_degree_2r(r):
+    """The radius-r central first derivative is exact on x^j for j <= 2r (the
+    derivative at 0 is 1 for j = 1, else 0) and not for j = 2r + 1."""
+    w = [Fraction(0)] + [Fraction((-1) ** (p + 1)) * Fraction(_fact(r) ** 2,
+                         p * _fact(r - p) * _fact(r + p)) for p in range(1, r + 1)]
+    assert np.allclose(O.fd_first_weights(r), [float(x) for x in w], rtol=0, atol=1e-16)
+    for j in range(0, 2 * r + 2):
+        d = sum(w[p] * (Fraction(p) ** j - Fraction(-p) ** j) for p in range(1, r + 1))
+        if j <= 2 * r:
+            assert d == (1 if j == 1 else 0), (r, j)
+        else:
+            assert d != 0
+
+
+def _fact(n):
+    from math import factorial
+    return factorial(n)
+
+
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET])
+def test_cc_force_against_dense_evaluation(bc):
+    """Per node, gamma_q = sum'_k c_k T_k(Hs_q) e_q from the eigendecomposition of
+    the dense node Hamiltonian (T_k = cos(k arccos), no recurrence), the box
+    gradient as an explicit matrix (Kronecker products of 1-D stencils), the
+    projectors read off whole-grid vectors, and the contraction in the
+    transposed form (D^T chi) . gamma."""
+    prob = synth.small_problem(61 + bc, n=(10, 9, 11), bc=bc, rcut=(2, 2, 2), n_atoms=2,
+                               rc=1.4, order=14, kT=0.3, fd_order=4)
+    lmin, lmax = _bounds(prob)
+    lf = 0.5 * (lmin + lmax) - 0.2 * (lmax - lmin)
+    rng = np.random.default_rng(3)
+    nodes = np.sort(rng.choice(prob.n_nodes, 40, replace=False))
+    f = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, prob.kT, lmin, lmax, prob.order)
+    N = prob.vshape
+    nv = int(np.prod(N))
+    chi_full = np.zeros((prob.n_atoms, prob.n_proj, nv))
+    for J in range(prob.n_atoms):
+        s0, s1 = prob.sup_off[J], prob.sup_off[J + 1]
+        for s in range(s0, s1):
+            chi_full[J, :, prob.sup_idx[s]] += prob.chi[s]
+    wp = O.fd_first_weights(prob.r)
+    ref = np.zeros_like(f)
+    hit = 0
+    for q in nodes:
+        lo, dims, ctr3 = O.node_box(prob, q, prob.rcut)
+        H, dims2, ctr = O.node_dense(prob, q, prob.rcut, lmin, lmax)
+        ev, U = np.linalg.eigh(H)
+        th = np.arccos(np.clip(ev, -1.0, 1.0))
+        fk = c[0] / 2 + sum(c[k] * np.cos(k * th) for k in range(1, prob.order + 1))
+        gam = U @ (fk * U[ctr])
+        # box -> whole-grid index of every box point (x fastest)
+        zz, yy, xx = np.meshgrid(*(np.arange(d) for d in dims[::-1]), indexing="ij")
+        g = [xx.ravel() + lo[0], yy.ravel() + lo[1], zz.ravel() + lo[2]]
+        if bc == synth.BC_PERIODIC:
+            g = [np.mod(g[a], N[a]) for a in range(3)]
+        gidx = g[0] + N[0] * (g[1] + N[1] * g[2])
+        for a in range(3):
+            D1 = np.zeros((dims[a], dims[a]))
+            for i in range(dims[a]):
+                for p in range(1, prob.r + 1):
+                    if i + p < dims[a]:
+                        D1[i, i + p] += wp[p] / prob.h[a]
+                    if i - p >= 0:
+                        D1[i, i - p] -= wp[p] / prob.h[a]
+            I = [np.eye(d) for d in dims]
+            mats = [I[2], I[1], I[0]]
+            mats[2 - a] = D1
+            D = np.kron(np.kron(mats[0], mats[1]), mats[2])
+            for J in range(prob.n_atoms):
+                chib = chi_full[J][:, gidx]                    # [n_proj, box]
+                chq = chib[:, ctr]
+                if not np.any(chq):
+                    continue
+                hit += 1
+                proj = (D.T @ chib.T).T @ gam                  # (D^T chi) . gamma
+                ref[J, a] += -4.0 * np.prod(prob.h) * np.sum(prob.c[J] * chq * proj)
+    assert hit > 0
+    assert np.abs(f).max() > 1e-6
+    assert np.abs(f - ref).max() <= 1e-11 * np.abs(ref).max()
