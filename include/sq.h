@@ -243,6 +243,23 @@ sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int
                                double *lambda_f, double *rho, double *u, double *s,
                                double *totals, void *stream);
 
+/* Nonlocal atomic force by the spectral Clenshaw-Curtis quadrature, Eq.
+ * (NLforceSQ) in the discrete form of Section 3:
+ *   f_J,nl = -4 sum_q e_q^T V_J^q grad_h (sum'_k c_k v_k^q),
+ * with v_k^q the Chebyshev vectors of the node's region (Eq. (Chebyshev)), c_k
+ * the Fermi-function coefficients at the Fermi level of the last
+ * sq_fermi_level (c_0 halved), grad_h the radius-r central first-derivative
+ * stencil, w_p = (-1)^{p+1} (r!)^2 / (p (r-p)! (r+p)!), on the region box with
+ * zero outside it, and e_q^T V_J^q f = h1 h2 h3 sum_lm c_Jl chi_Jlm(q)
+ * (chi_Jlm . f) over the box.  Only nodes inside some projector support
+ * contribute; sq_setup lists them.  The recurrence runs in params.precision;
+ * the contraction and the accumulation are FP64.
+ *   f_nl  device [n_atoms][3] FP64 output (overwritten).
+ * Errors: SQ_ERR_STATE without sq_density and sq_fermi_level before it,
+ * SQ_ERR_ARG without projectors or for FP64 regions of edge above 21 (the
+ * box and the projector tables must share the LDS). */
+sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream);
+
 /* Synchronises the context's last stream and returns the device-side status
  * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */
 sq_status sq_device_status(sq_ctx *ctx);

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "SQ_OK", -1: "SQ_ERR_ARG", -2: "SQ_ERR_HIP", -3: "SQ_ERR_OOM"
 
 # every entry point declared in include/sq.h
 EXPORTS = ("sq_setup", "sq_destroy", "sq_last_error", "sq_get_info", "sq_density",
-           "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level",
+           "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level", "sq_nonlocal_force",
            "sq_density_backward", "sq_device_status")
 
 
@@ -82,6 +82,8 @@ def lib():
         L.sq_gauss_density.restype = C.c_int
         L.sq_gauss_fermi_level.argtypes = [VP, D, D, I32, VP, VP, VP, VP, VP, VP]
         L.sq_gauss_fermi_level.restype = C.c_int
+        L.sq_nonlocal_force.argtypes = [VP, VP, VP]
+        L.sq_nonlocal_force.restype = C.c_int
         L.sq_density_backward.argtypes = [VP, VP, VP, VP, VP, VP]
         L.sq_density_backward.restype = C.c_int
         L.sq_device_status.argtypes = [VP]
@@ -140,6 +142,10 @@ def sq_gauss_fermi_level(ctx, Ne, tol, max_iter, lf_ptr, rho_ptr, u_ptr, s_ptr, 
                          stream):
     return check(lib().sq_gauss_fermi_level(ctx, Ne, tol, max_iter, lf_ptr, rho_ptr, u_ptr,
                                             s_ptr, totals_ptr, stream))
+
+
+def sq_nonlocal_force(ctx, f_ptr, stream):
+    return check(lib().sq_nonlocal_force(ctx, f_ptr, stream))
 
 
 def sq_density_backward(ctx, g_rho_ptr, g_u_ptr, dV_ptr, dR_ptr, stream):

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "sq_force.h"
 #include "sq_kernels.h"
 
 using namespace sqk;
@@ -56,6 +57,17 @@ void fd_weights(int r, double *w) {
         s += w[p];
     }
     w[0] = -2.0 * s;
+}
+
+// central first-derivative weights of radius r (the FD gradient of Section 3):
+// w_p = (-1)^{p+1} (r!)^2 / (p (r-p)! (r+p)!), applied as sum_p w_p (f_{+p} - f_{-p}) / h
+void fd_first_weights(int r, double *w) {
+    w[0] = 0.0;
+    for (int p = 1; p <= r; ++p) {
+        double f = 1.0;
+        for (int j = 1; j <= p; ++j) f *= double(r - p + j) / double(r + j);
+        w[p] = ((p % 2) ? 1.0 : -1.0) * f / double(p);
+    }
 }
 
 }  // namespace
@@ -162,6 +174,9 @@ struct sq_ctx {
     double *d_glam = nullptr, *d_gwgt = nullptr, *d_gpart = nullptr;
     double *glam_last = nullptr, *gwgt_last = nullptr;
     bool have_gauss = false;
+    // nonlocal force: the regions of nodes inside some projector support
+    Item *d_fitems = nullptr;
+    std::vector<Group> fgroups;
     hipStream_t last_stream = nullptr;
 
     template <typename T>
@@ -778,6 +793,32 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     }
     c.groups = c.plan == PLAN_SPLIT ? split : merged;
 
+    // nonlocal force work list: nodes where some chi_Jlm is nonzero, one
+    // launch per edge bucket
+    if (c.n_atoms) {
+        std::vector<char> covered(c.nv, 0);
+        for (int64_t g : sup_idx) covered[g] = 1;
+        std::vector<Item> fitems;
+        for (const Item &it : items) {
+            int64_t g[3];
+            for (int a = 0; a < 3; ++a) {
+                g[a] = it.lo[a] + it.ctr[a];
+                if (c.periodic) g[a] = ((g[a] % c.N[a]) + c.N[a]) % c.N[a];
+            }
+            if (covered[g[0] + (int64_t)c.N[0] * (g[1] + (int64_t)c.N[1] * g[2])])
+                fitems.push_back(it);
+        }
+        if (!fitems.empty()) {
+            UPLOAD(c.d_fitems, fitems.data(), fitems.size());
+            c.fgroups = make_groups(fitems, PLAN_SPLIT);
+            for (Group &g : c.fgroups) {
+                if (!cc_force_supported(c.prec, g.E)) continue;
+                const int occ = cc_force_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
+                g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+            }
+        }
+    }
+
     // adjoint: one vector slot per resident workgroup, shared by the groups
     c.adj_ok = true;
     for (const Group &g : c.groups) c.adj_ok = c.adj_ok && g.E <= adjoint_max_edge(c.aprec);
@@ -1018,6 +1059,49 @@ sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int
                           max_iter, lambda_f, st));
     HIP_TRY(k_gauss_fields(c.glam_last, c.gwgt_last, c.n_nodes, c.K, c.p.kT, c.d_scal, rho, u, s,
                            c.d_gpart, N_PARTIAL, totals, lambda_f, st));
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream) {
+    if (!ctx) return fail(SQ_ERR_ARG, "ctx is NULL");
+    if (!f_nl) return fail(SQ_ERR_ARG, "f_nl is NULL");
+    sq_ctx &c = *ctx;
+    if (!c.have_fermi)
+        return fail(SQ_ERR_STATE, "sq_nonlocal_force needs sq_density and sq_fermi_level first");
+    if (c.n_atoms == 0) return fail(SQ_ERR_ARG, "the context has no projectors");
+    for (const Group &g : c.fgroups)
+        if (!cc_force_supported(c.prec, g.E))
+            return fail(SQ_ERR_ARG, "the %s nonlocal force supports region edges up to %d (this "
+                        "work list: %d)", c.prec == SQ_FP64 ? "FP64" : "FP32",
+                        c.prec == SQ_FP64 ? 21 : 32, g.E);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(k_fill_f64(f_nl, 0.0, 3 * (int64_t)c.n_atoms, st));
+    if (c.fgroups.empty()) return SQ_OK;
+    ForceParams fp{};
+    double w1[MAX_R + 1];
+    fd_first_weights(c.r, w1);
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p <= MAX_R; ++p) fp.grad[a][p] = p <= c.r ? w1[p] / c.p.h[a] : 0.0;
+    fp.cp = c.fw.cp;
+    fp.force = f_nl;
+    HIP_TRY(k_fill_i32(c.d_counter, 0, (int64_t)c.fgroups.size(), st));
+    auto launch = [&](auto tag) -> sq_status {
+        using T = decltype(tag);
+        for (size_t g = 0; g < c.fgroups.size(); ++g) {
+            RegionArgs<T> a{};
+            fill_region_args(c, a);
+            a.items = c.d_fitems + c.fgroups[g].begin;
+            a.n_items = c.fgroups[g].count;
+            a.counter = c.d_counter + g;
+            a.moments = nullptr;
+            HIP_TRY(launch_cc_force(c.prec, c.fgroups[g].E, c.r, c.fgroups[g].maskz, &a, fp,
+                                    c.fgroups[g].grid_fwd, st));
+        }
+        return SQ_OK;
+    };
+    if (c.prec == SQ_FP64) TRY(launch(double{}));
+    else TRY(launch(float{}));
     c.last_stream = st;
     return SQ_OK;
 }

@@ -169,6 +169,14 @@ class Context:
                                _ptr(rho), _ptr(u), _ptr(s), _ptr(totals), _stream())
         return lambda_f, rho, u, s, totals
 
+    def nonlocal_force(self, f: Optional[torch.Tensor] = None, device=None):
+        """sq_nonlocal_force: Clenshaw-Curtis nonlocal force [n_atoms, 3] (FP64)."""
+        dev = device or torch.device("cuda")
+        if f is None:
+            f = torch.empty((max(self.n_atoms, 1), 3), dtype=torch.float64, device=dev)
+        L.sq_nonlocal_force(self.ctx, _ptr(f), _stream())
+        return f[:self.n_atoms]
+
     def backward(self, g_rho: Optional[torch.Tensor], g_u: Optional[torch.Tensor],
                  dV: Optional[torch.Tensor] = None, dR: Optional[torch.Tensor] = None):
         """sq_density_backward: accumulates into dV (V grid) and dR [n_atoms, 3]."""

@@ -1,0 +1,109 @@
+"""Clenshaw-Curtis nonlocal force, Eq. (NLforceSQ), through the C ABI against
+the FP64 oracle.
+
+sq_nonlocal_force after sq_density / sq_fermi_level (lambda_f given) against
+oracle.cc_nonlocal_force on the same seeded inputs.  Tolerances, max norm
+relative to max |f|: FP64 1e-10; FP32 vectors 1e-4 (the force differences
+gamma across the stencil and sums signed terms over the support, which costs
+about an order of magnitude over the 1e-5 of rho).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2011_13517_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu_force(prob, precision, lmin, lmax, lf, nodes=None, node_rcut=None):
+    from paper_2011_13517_amd import sq
+    ctx = sq.Context(prob, precision=precision, nodes=nodes, node_rcut=node_rcut)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    ctx.density(V, lmin, lmax)
+    lam = torch.tensor([lf], dtype=torch.float64, device="cuda")
+    ctx.fermi_level(max_iter=0, lambda_f=lam, want_fields=False)
+    f = ctx.nonlocal_force()
+    torch.cuda.synchronize()
+    ctx.status()
+    out = f.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def _tol(precision):
+    return 1e-10 if precision == 0 else 1e-4
+
+
+@pytest.mark.parametrize("bc", [synth.BC_PERIODIC, synth.BC_DIRICHLET, synth.BC_EMBEDDED])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_force_small_all_nodes(bc, precision):
+    print(f"[case] force small bc={bc} precision={precision}", flush=True)
+    prob = synth.small_problem(61 + bc, n=(12, 12, 13), bc=bc, rcut=(2, 2, 2), n_atoms=3,
+                               rc=1.4, order=14, kT=0.3, fd_order=4)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    lf = 0.5 * (lmin + lmax) - 0.2 * (lmax - lmin)
+    f = _gpu_force(prob, precision, lmin, lmax, lf)
+    ref = O.cc_nonlocal_force(prob, lmin, lmax, lf)
+    scale = np.abs(ref).max()
+    assert scale > 1e-6
+    assert np.abs(f - ref).max() <= _tol(precision) * scale
+
+
+def test_force_uneven_regions_fp64():
+    """Per-node widths: several edge buckets and launch groups, 12th-order FD."""
+    print("[case] force uneven", flush=True)
+    base = synth.small_problem(24, n=(20, 18, 22), rcut=(4, 4, 4), n_atoms=5, rc=1.6, order=12,
+                               kT=0.25, fd_order=12)
+    rng = np.random.default_rng(6)
+    nodes = np.sort(rng.choice(int(np.prod(base.n)), 400, replace=False)).astype(np.int64)
+    nr = rng.integers(1, 5, size=(400, 3)).astype(np.int32)
+    lmin, lmax = O.lanczos_bounds(base, steps=60)
+    lf = 0.5 * (lmin + lmax) - 0.25 * (lmax - lmin)
+    f = _gpu_force(base, 0, lmin, lmax, lf, nodes=nodes, node_rcut=nr)
+    ref = O.cc_nonlocal_force(base, lmin, lmax, lf, nodes=nodes, node_m=nr)
+    assert np.abs(ref).max() > 0
+    assert np.abs(f - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_force_config2_node_subset_fp32():
+    """The 64^3 workload's geometry (27^3 regions, r = 6, 96 atoms, K = 100,
+    FP32; the kernel instance the full run uses) on the 60 nodes nearest to
+    atom 0: every node's contribution lands on the atoms around it."""
+    print("[case] force config2 subset", flush=True)
+    prob = synth.config(2)
+    n = np.asarray(prob.n)
+    pos = np.asarray(prob.atom_pos[0]) / np.asarray(prob.h)
+    grid = np.stack(np.meshgrid(*(np.arange(k) for k in n), indexing="ij"), -1).reshape(-1, 3)
+    d = np.abs(grid - pos[None, :])
+    d = np.minimum(d, n[None, :] - d)
+    idx = np.argsort((d ** 2).sum(1))[:60]
+    nodes = np.sort(grid[idx, 0] + n[0] * (grid[idx, 1] + n[1] * grid[idx, 2])).astype(np.int64)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    lf = 0.5 * (lmin + lmax) - 0.45 * (lmax - lmin)
+    f = _gpu_force(prob, 1, lmin, lmax, lf, nodes=nodes)
+    ref = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
+    assert np.abs(ref[0]).max() > 0
+    assert np.abs(f - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+def test_force_errors():
+    from paper_2011_13517_amd import sq
+    from paper_2011_13517_amd._lib import SQError
+    prob = synth.small_problem(3, n=(10, 10, 10), rcut=(2, 2, 2), n_atoms=2, rc=1.3, order=6)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    ctx = sq.Context(prob, precision=0)
+    with pytest.raises(SQError):        # no Fermi level yet
+        ctx.nonlocal_force()
+    ctx.close()
+    bare = dataclasses.replace(prob, n_atoms=0, sup_off=None, sup_idx=None, chi=None, dchi=None,
+                               c=None, atom_pos=None)
+    ctx = sq.Context(bare, precision=0)
+    ctx.density(V, -5.0, 40.0)
+    ctx.fermi_level(max_iter=0, lambda_f=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(SQError):        # no projectors
+        ctx.nonlocal_force()
+    ctx.close()
