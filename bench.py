@@ -70,6 +70,47 @@ def recorded_traffic(kernel):
             "bytes": k["fetch_bytes"] + k["write_bytes"], "source": os.path.basename(path)}
 
 
+def force_leg(ctx, prob, f_app, tot, lf, dev):
+    """Clenshaw-Curtis nonlocal force (sq_nonlocal_force) at the Fermi level of
+    the last timed step, timed with HIP events on the current stream."""
+    import torch
+    info = ctx.info
+    f = torch.empty((ctx.n_atoms, 3), dtype=torch.float64, device=dev)
+    ctx.nonlocal_force(f)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.nonlocal_force(f)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.status()
+    t = e0.elapsed_time(e1) * 1e-3
+    nf, pts = int(info.n_force_nodes), int(info.force_region_points)
+    achieved = pts * ctx.K * f_app / t / 1e12
+    log(f"nonlocal force: {nf} nodes in supports, {t:.3f} s")
+    # the oracle on the 4 nodes nearest to atom 0 (all inside its support)
+    import oracle as O
+    n = np.asarray(prob.n)
+    pos = np.asarray(prob.atom_pos[0]) / np.asarray(prob.h)
+    grid = np.stack(np.meshgrid(*(np.arange(k) for k in n), indexing="ij"), -1).reshape(-1, 3)
+    d = np.abs(grid - pos[None, :])
+    d = np.minimum(d, n[None, :] - d) if prob.bc == 0 else d
+    idx = np.argsort((d ** 2).sum(1))[:4]
+    nodes = grid[idx, 0] + n[0] * (grid[idx, 1] + n[1] * grid[idx, 2])
+    om, tau = float(tot[4]), float(tot[5])
+    t_o = time.perf_counter()
+    O.cc_nonlocal_force(prob, om - tau, om + tau, lf, nodes=nodes)
+    t_o = time.perf_counter() - t_o
+    cpu = dict(value=nodes.size * ctx.K / t_o, unit="node-steps/s", cores=1,
+               kind="oracle", sample=f"{nodes.size} nodes nearest to atom 0 ({t_o:.1f} s)")
+    return {"seconds": t, "force_nodes": nf, "node_steps_per_s": nf * ctx.K / t,
+            "cpu_baseline": cpu,
+            "roofline": dict(bound="alu", kernel="cc_force_kernel", achieved=achieved,
+                             peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
+                             frac=achieved / (PEAK_FP32_VALU / 1e12), traffic=None),
+            "max_abs_f": float(f.abs().max().item())}
+
+
 def gauss_leg(ctx, prob, V, tot, f_app, region_points, dev):
     """Gauss-quadrature density on the same workload and context: K Lanczos
     steps per node (sq_gauss_density: bounds as in the Chebyshev run, the
@@ -102,7 +143,9 @@ def gauss_leg(ctx, prob, V, tot, f_app, region_points, dev):
         f"N_e={gt[0]:.10f} lambda_f={lf.item():.10f}")
     rng = np.random.default_rng(13)
     sample = np.sort(rng.choice(n, 4, replace=False))
+    t_o = time.perf_counter()
     lam_o, w_o = O.gauss_rules(prob, lmin, lmax, K, nodes=prob.node_list()[sample])
+    t_o = time.perf_counter() - t_o
     rho_o, u_o, s_o = O.gauss_fields(lam_o, w_o, lf.item(), prob.kT)
     rho_g = rho.cpu().numpy()
     achieved = region_points * K * f_app / t_rules / 1e12
@@ -121,6 +164,10 @@ def gauss_leg(ctx, prob, V, tot, f_app, region_points, dev):
                      "sample_nodes": int(sample.size),
                      "reference": "FP64 oracle Gauss rules at the GPU's lambda_f"},
         "precision": "FP32 Lanczos vectors, FP64 a_k, b_k, eigensolve, bisection, fields",
+        "cpu_baseline": dict(value=sample.size * K / t_o, unit="node-steps/s", cores=1,
+                             kind="oracle",
+                             sample=f"{sample.size} random nodes, oracle Lanczos + tridiagonal "
+                                    f"eigensolve ({t_o:.1f} s)"),
     }
 
 
@@ -132,6 +179,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-force", action="store_true",
+                    help="skip the Clenshaw-Curtis nonlocal-force leg")
     ap.add_argument("--no-gauss", action="store_true",
                     help="skip the Gauss-quadrature (LSSGQ) leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
@@ -245,6 +294,8 @@ def main():
 
     # accuracy against the FP64 oracle on sampled nodes
     extra = {}
+    if not args.no_force and prob.n_atoms:
+        extra["cc_force"] = force_leg(ctx, prob, f_app, tot, lam_v.item(), dev)
     if not args.no_gauss:
         extra["lssgq"] = gauss_leg(ctx, prob, V, tot, f_app, region_points, dev)
     rho_np = rho.cpu().numpy()

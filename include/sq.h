@@ -114,6 +114,9 @@ typedef struct {
     int64_t region_points;  /* sum over nodes of the region size |R_q|                 */
     int64_t workspace_bytes;/* device memory held by the context                       */
     int32_t n_launches;     /* persistent region launches per pass (the launch plan)   */
+    int32_t pad_;
+    int64_t n_force_nodes;  /* nodes inside some projector support (sq_nonlocal_force) */
+    int64_t force_region_points; /* sum of their region sizes                          */
 } sq_info;
 
 /* Builds a context: validates parameters, builds the region work list and

@@ -177,6 +177,7 @@ struct sq_ctx {
     // nonlocal force: the regions of nodes inside some projector support
     Item *d_fitems = nullptr;
     std::vector<Group> fgroups;
+    int64_t n_force_nodes = 0, force_region_points = 0;
     hipStream_t last_stream = nullptr;
 
     template <typename T>
@@ -805,9 +806,12 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
                 g[a] = it.lo[a] + it.ctr[a];
                 if (c.periodic) g[a] = ((g[a] % c.N[a]) + c.N[a]) % c.N[a];
             }
-            if (covered[g[0] + (int64_t)c.N[0] * (g[1] + (int64_t)c.N[1] * g[2])])
+            if (covered[g[0] + (int64_t)c.N[0] * (g[1] + (int64_t)c.N[1] * g[2])]) {
                 fitems.push_back(it);
+                c.force_region_points += (int64_t)it.dim[0] * it.dim[1] * it.dim[2];
+            }
         }
+        c.n_force_nodes = (int64_t)fitems.size();
         if (!fitems.empty()) {
             UPLOAD(c.d_fitems, fitems.data(), fitems.size());
             c.fgroups = make_groups(fitems, PLAN_SPLIT);
@@ -892,6 +896,9 @@ sq_status sq_get_info(const sq_ctx *ctx, sq_info *info) {
     info->region_points = ctx->region_points;
     info->workspace_bytes = ctx->bytes;
     info->n_launches = (int32_t)ctx->groups.size();
+    info->pad_ = 0;
+    info->n_force_nodes = ctx->n_force_nodes;
+    info->force_region_points = ctx->force_region_points;
     return SQ_OK;
 }
 
