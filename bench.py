@@ -37,7 +37,7 @@ def log(msg):
 KERNEL_SOURCES = ("sq_internal.h", "sq_region.h", "sq_forward.hip", "sq_adjoint_kernel.h",
                   "sq_adjoint.hip", "sq_adjoint_r1.hip", "sq_adjoint_r2.hip", "sq_adjoint_r3.hip",
                   "sq_adjoint_r4.hip", "sq_adjoint_r5.hip", "sq_adjoint_r6.hip",
-                  "sq_gauss_lanczos.hip", "sq_gauss.hip")
+                  "sq_gauss_lanczos.hip", "sq_gauss.hip", "sq_force.h", "sq_force.hip")
 
 
 def kernel_source_hash():
@@ -107,7 +107,8 @@ def force_leg(ctx, prob, f_app, tot, lf, dev):
             "cpu_baseline": cpu,
             "roofline": dict(bound="alu", kernel="cc_force_kernel", achieved=achieved,
                              peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
-                             frac=achieved / (PEAK_FP32_VALU / 1e12), traffic=None),
+                             frac=achieved / (PEAK_FP32_VALU / 1e12),
+                             traffic=recorded_traffic("cc_force_kernel")),
             "max_abs_f": float(f.abs().max().item())}
 
 

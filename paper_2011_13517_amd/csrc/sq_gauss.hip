@@ -287,11 +287,19 @@ hipError_t k_gauss_eig(double *lam, double *wgt, int64_t n, int K, const Scalars
     if (n == 0) return hipSuccess;
     const int nt = gauss_eig_threads(K);
     const size_t lds = (size_t)nt * 3 * K * sizeof(double);
+    // more than 64 KiB of dynamic LDS needs the kernel attribute raised, once per
+    // device (a host call: it is kept out of every later, possibly captured, call)
+    static bool raised[64] = {};
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void *)gauss_eig_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 LDS_BYTES);
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
+        if (dev >= 64 || !raised[dev]) {
+            e = hipFuncSetAttribute((const void *)gauss_eig_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+            if (e != hipSuccess) return e;
+            if (dev < 64) raised[dev] = true;
+        }
     }
     const int64_t grid = (n + nt - 1) / nt;
     hipLaunchKernelGGL(gauss_eig_kernel, dim3((unsigned)grid), dim3(nt), lds, st, lam, wgt, n, K, s,

@@ -154,17 +154,21 @@ class Context:
 
     def gauss_fermi_level(self, Ne: float = 0.0, tol: float = 1e-10, max_iter: int = 200,
                           lambda_f: Optional[torch.Tensor] = None, want_fields: bool = True,
-                          device=None):
+                          device=None, rho: Optional[torch.Tensor] = None,
+                          u: Optional[torch.Tensor] = None, s: Optional[torch.Tensor] = None,
+                          totals: Optional[torch.Tensor] = None):
         """sq_gauss_fermi_level: (lambda_f[1], rho[n], u[n], s[n], totals[8]) with
-        totals = {N_e, U, S, U - kT S, omega, tau, iterations, status}."""
+        totals = {N_e, U, S, U - kT S, omega, tau, iterations, status} (outputs are
+        allocated unless given)."""
         dev = device or torch.device("cuda")
         if lambda_f is None:
             lambda_f = torch.zeros(1, dtype=torch.float64, device=dev)
-        rho = u = s = None
         if want_fields:
-            rho, u, s = (torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
-                         for _ in range(3))
-        totals = torch.empty(8, dtype=torch.float64, device=dev)
+            rho, u, s = (t if t is not None else
+                         torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+                         for t in (rho, u, s))
+        if totals is None:
+            totals = torch.empty(8, dtype=torch.float64, device=dev)
         L.sq_gauss_fermi_level(self.ctx, float(Ne), float(tol), int(max_iter), _ptr(lambda_f),
                                _ptr(rho), _ptr(u), _ptr(s), _ptr(totals), _stream())
         return lambda_f, rho, u, s, totals

@@ -123,3 +123,68 @@ def test_graph_replay_matches_eager(precision):
             assert (a - b).abs().max().item() <= tol * scale, (rep, i)
         assert abs(got[5][0].item() - Ne) < 1e-8
     ctx.close()
+
+
+def test_graph_replay_gauss_and_force():
+    """The Gauss-quadrature rules, their Fermi level and fields, and the
+    Clenshaw-Curtis nonlocal force captured in one HIP graph (after an eager
+    warm-up that makes the one-time allocations) and replayed on changed inputs,
+    each replay checked against the eager result (FP64)."""
+    from paper_2011_13517_amd import sq
+    print("[case] graph replay gauss + force", flush=True)
+    prob = _problem()
+    Ne = 0.3 * prob.n_nodes
+    ctx = sq.Context(prob, precision=0)
+    dev = torch.device("cuda")
+    n, K = ctx.n_nodes, ctx.K
+    V0 = torch.tensor(prob.V, dtype=torch.float64, device=dev)
+    V = V0.clone()
+    mu = torch.empty((n, K + 1), dtype=torch.float64, device=dev)
+    lam = torch.zeros(1, dtype=torch.float64, device=dev)
+    glam = torch.zeros(1, dtype=torch.float64, device=dev)
+    nodes = torch.empty((n, K), dtype=torch.float64, device=dev)
+    wts = torch.empty_like(nodes)
+    rho, u, s = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+    tot = torch.empty(8, dtype=torch.float64, device=dev)
+    f = torch.empty((prob.n_atoms, 3), dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.density(V, math.nan, math.nan, moments=mu)
+        ctx.fermi_level(Ne=Ne, tol=1e-9, max_iter=200, lambda_f=lam, want_fields=False)
+        ctx.nonlocal_force(f)
+        ctx.gauss_density(V, math.nan, math.nan, nodes=nodes, weights=wts)
+        ctx.gauss_fermi_level(Ne=Ne, tol=1e-9, max_iter=200, lambda_f=glam, rho=rho, u=u, s=s,
+                              totals=tot)
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return [t.clone() for t in (nodes, wts, glam, rho, u, s, tot, f)]
+
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        step()
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        pert = torch.tensor(rng.uniform(-0.05, 0.05, size=prob.V.shape), device=dev)
+        V.copy_(V0 + pert)
+        graph.replay()
+        got = snapshot()
+        step()
+        ref = snapshot()
+        assert ctx.status() == 0
+        # projector dot products (both sweeps) and the force sums use atomics, so
+        # low-order bits may differ; a stale input would differ by O(0.05)
+        for i, (a, b) in enumerate(zip(got, ref)):
+            if i == 6:
+                a, b = a[:6], b[:6]
+            tol = 1e-11
+            scale = max(b.abs().max().item(), 1.0)
+            assert (a - b).abs().max().item() <= tol * scale, (rep, i)
+        assert abs(got[6][0].item() - Ne) < 1e-8
+    ctx.close()

@@ -174,3 +174,28 @@ def test_gauss_state_errors():
     with pytest.raises(SQError):
         ctx.gauss_fermi_level(Ne=1.0)
     ctx.close()
+
+
+def test_gauss_rules_integrate_gpu_moments():
+    """Gauss exactness on the GPU alone: the K-point rules of sq_gauss_density
+    integrate T_j exactly for j <= 2K - 1, so sum_k w_k T_j(theta_k) equals the
+    Chebyshev moments mu_j of sq_density on the same regions (FP64)."""
+    from paper_2011_13517_amd import sq
+    print("[case] gauss rules vs GPU moments", flush=True)
+    K = 8
+    prob = synth.small_problem(17, n=(11, 12, 10), rcut=(2, 2, 2), n_atoms=3, rc=1.3, order=K,
+                               kT=0.2, fd_order=6)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    om, tau = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    g = _gpu(prob, 0, lmin, lmax)
+    ctx = sq.Context(dataclasses.replace(prob, order=2 * K + 1), precision=0)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    mu, _ = ctx.density(V, lmin, lmax)
+    torch.cuda.synchronize()
+    mu = mu.cpu().numpy()
+    ctx.close()
+    th = np.arccos(np.clip((g["lam"] - om) / tau, -1.0, 1.0))
+    for j in range(2 * K):
+        got = np.sum(g["w"] * np.cos(j * th), axis=1)
+        assert np.abs(got - mu[:, j]).max() <= 1e-10, j
+    assert np.abs(np.sum(g["w"] * np.cos(2 * K * th), axis=1) - mu[:, 2 * K]).max() > 1e-8
