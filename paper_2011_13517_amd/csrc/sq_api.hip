@@ -1078,10 +1078,13 @@ sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream) {
         return fail(SQ_ERR_STATE, "sq_nonlocal_force needs sq_density and sq_fermi_level first");
     if (c.n_atoms == 0) return fail(SQ_ERR_ARG, "the context has no projectors");
     for (const Group &g : c.fgroups)
-        if (!cc_force_supported(c.prec, g.E))
+        if (!cc_force_supported(c.prec, g.E)) {
+            int emax = 0;
+            for (int e : {9, 13, 17, 21, 27, 32})
+                if (cc_force_supported(c.prec, e)) emax = e;
             return fail(SQ_ERR_ARG, "the %s nonlocal force supports region edges up to %d (this "
-                        "work list: %d)", c.prec == SQ_FP64 ? "FP64" : "FP32",
-                        c.prec == SQ_FP64 ? 21 : 32, g.E);
+                        "work list: %d)", c.prec == SQ_FP64 ? "FP64" : "FP32", emax, g.E);
+        }
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(k_fill_f64(f_nl, 0.0, 3 * (int64_t)c.n_atoms, st));
     if (c.fgroups.empty()) return SQ_OK;

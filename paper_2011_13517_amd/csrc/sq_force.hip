@@ -39,7 +39,11 @@ cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
     constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
     constexpr int MAXAT = max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>();
     constexpr int AT = MAXAT > 0 ? MAXAT : 1;
-    constexpr bool DREG = sizeof(T) == 4 || E <= 17;
+    // gamma takes E more VGPRs than the forward sweep: the diagonal is re-read
+    // from L2 at the largest FP32 edge, and the stencil recomputes its neighbour
+    // offsets per step (low-register variant), instead of spilling
+    constexpr bool DREG = (sizeof(T) == 4 && E <= 21) || E <= 17;
+    constexpr bool LOWREG = E >= 27;
     if constexpr (!force_supported<T, E>()) {
         return;
     } else {
@@ -150,16 +154,16 @@ cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
         // Chebyshev sweep (the newest vector alternates between v and w),
         // gamma += c'_k v_k after every step
         for (int k = 0; k < K; k += 2) {
-            region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false>(a, c, d, col, plane, gz0, n2,
-                                                                    v, w, lds, nl, k == 0);
+            region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
+                a, c, d, col, plane, gz0, n2, v, w, lds, nl, k == 0);
             {
                 const T ck = (T)fp.cp[k + 1];
 #pragma unroll
                 for (int z = 0; z < E; ++z) g[z] += ck * w[z];
             }
             if (k + 1 < K) {
-                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false>(a, c, d, col, plane, gz0,
-                                                                        n2, w, v, lds, nl, false);
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
+                    a, c, d, col, plane, gz0, n2, w, v, lds, nl, false);
                 const T ck = (T)fp.cp[k + 2];
 #pragma unroll
                 for (int z = 0; z < E; ++z) g[z] += ck * v[z];
