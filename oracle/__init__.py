@@ -439,6 +439,103 @@ def cc_nonlocal_force(prob, lmin, lmax, lambda_f, nodes=None, node_m=None, V=Non
     return f
 
 
+# --------------------------------------------------------------------------- #
+# SCF outer loop (Section 3's flowchart): Poisson, LDA exchange-correlation,
+# mixing of the effective potential -- periodic cells only
+# --------------------------------------------------------------------------- #
+def fd_laplacian_symbol(n, h, r):
+    """Eigenvalues of the periodic FD Laplacian (Section 3's stencil) on the
+    discrete Fourier modes, [n2][n1][n0]: sum_a (w_0 + 2 sum_p w_p cos(2 pi p k_a / n_a)) / h_a^2."""
+    w = fd_weights(r)
+    parts = []
+    for a in range(3):
+        k = np.arange(n[a])
+        s = np.full(n[a], w[0])
+        for p in range(1, r + 1):
+            s = s + 2.0 * w[p] * np.cos(2.0 * np.pi * p * k / n[a])
+        parts.append(s / (h[a] * h[a]))
+    return parts[2][:, None, None] + parts[1][None, :, None] + parts[0][None, None, :]
+
+
+def poisson_periodic(f, n, h, r):
+    """phi with -Lap_h phi = 4 pi f on the periodic grid, Eq. (Poisson) with the FD
+    Laplacian; f is projected to zero mean (the neutral cell) and phi has zero
+    mean.  Solved exactly in the discrete Fourier basis (an FFT as library step)."""
+    F = np.fft.fftn(np.asarray(f, np.float64).reshape(n[2], n[1], n[0]))
+    L = fd_laplacian_symbol(n, h, r)
+    F[0, 0, 0] = 0.0
+    L[0, 0, 0] = 1.0
+    return np.real(np.fft.ifftn(-4.0 * np.pi * F / L)).reshape(-1)
+
+
+PW92 = dict(A=0.031091, a1=0.21370, b1=7.5957, b2=3.5876, b3=1.6382, b4=0.49294)
+
+
+def lda_pw92(n):
+    """LDA exchange-correlation energy per electron and potential, unpolarised:
+    Slater exchange e_x = -(3/4)(3 n / pi)^(1/3), v_x = (4/3) e_x, and the
+    Perdew-Wang (1992) fit of the Ceperley-Alder correlation,
+    e_c = -2A(1 + a1 rs) ln(1 + 1 / (2A(b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2))),
+    v_c = e_c - (rs / 3) de_c/drs, rs = (3 / (4 pi n))^(1/3).  Zero where n <= 0."""
+    n = np.asarray(n, np.float64)
+    exc = np.zeros_like(n)
+    vxc = np.zeros_like(n)
+    m = n > 0.0
+    x = n[m]
+    ex = -0.75 * np.cbrt(3.0 * x / np.pi)
+    rs = np.cbrt(3.0 / (4.0 * np.pi * x))
+    c = PW92
+    sr = np.sqrt(rs)
+    q0 = -2.0 * c["A"] * (1.0 + c["a1"] * rs)
+    q1 = 2.0 * c["A"] * (c["b1"] * sr + c["b2"] * rs + c["b3"] * rs * sr + c["b4"] * rs * rs)
+    dq1 = c["A"] * (c["b1"] / sr + 2.0 * c["b2"] + 3.0 * c["b3"] * sr + 4.0 * c["b4"] * rs)
+    lg = np.log1p(1.0 / q1)
+    ec = q0 * lg
+    dec = -2.0 * c["A"] * c["a1"] * lg - q0 * dq1 / (q1 * q1 + q1)
+    exc[m] = ex + ec
+    vxc[m] = 4.0 / 3.0 * ex + ec - rs / 3.0 * dec
+    return exc, vxc
+
+
+def scf(prob, b, Ne, V0, lmin, lmax, beta=0.3, tol=1e-6, max_iter=30, anderson=True,
+        fermi_tol=1e-10):
+    """Fixed-point iteration on the effective potential (Section 3's flowchart):
+    V_in -> moments (Eq. (Chebyshev)) -> lambda_f (Eq. (Ne)) -> rho^q (Eq. (rhoq))
+    -> n = rho^q / (h1 h2 h3) -> phi of Eq. (Poisson) with source n + b -> V_out =
+    phi + v_xc(n) -> mixing.  Mixing: F = V_out - V_in; the first step is linear,
+    V <- V + beta F; later steps are Anderson with one previous pair,
+    g = F.(F - F') / |F - F'|^2, V <- (V - g (V - V')) + beta (F - g (F - F')).
+    Stops when the RMS of F is below tol.  Every node of the periodic cell is a
+    quadrature node; (lmin, lmax) stay fixed.  Returns one record per iteration."""
+    V = np.array(V0, np.float64)
+    h3 = float(np.prod(prob.h))
+    Vp = Fp = None
+    recs = []
+    for it in range(max_iter):
+        mu = moments(prob, lmin, lmax, V=V)
+        lf, _ = fermi_level(mu.sum(0), prob.kT, lmin, lmax, Ne, tol=fermi_tol)
+        cg, _ = cheb_coeffs(KIND_G, lf, prob.kT, lmin, lmax, prob.order)
+        rho_q, _ = contract(mu, cg, cg)
+        n_x = rho_q / h3
+        phi = poisson_periodic(n_x + b, prob.n, prob.h, prob.r)
+        _, vxc = lda_pw92(n_x)
+        Vout = phi + vxc
+        F = Vout - V
+        res = float(np.sqrt(np.mean(F * F)))
+        recs.append(dict(V_in=V.copy(), V_out=Vout, rho=rho_q, lambda_f=lf, residual=res))
+        if res < tol:
+            break
+        if Fp is None or not anderson:
+            Vn = V + beta * F
+        else:
+            dV, dF = V - Vp, F - Fp
+            g = float(F @ dF) / float(dF @ dF)
+            Vn = (V - g * dV) + beta * (F - g * dF)
+        Vp, Fp = V, F
+        V = Vn
+    return recs
+
+
 def adjoint(prob, lmin, lmax, a, nodes=None, node_m=None, V=None, with_dR=True):
     """(dV, dR) of y = sum_q sum_k a[q,k] mu_k^q at fixed lambda_f, omega, tau."""
     b = _Bound(prob)

@@ -382,6 +382,21 @@ def _config5(rng):
     return prob
 
 
+def pseudocharge(prob: Problem, Z=None, sigma=1.0) -> np.ndarray:
+    """Seeded stand-in for the nuclei's pseudocharge density b(x) on a periodic
+    grid: a normalised Gaussian of charge -Z_J per atom (periodic images
+    summed), rescaled so that sum_x b(x) h1 h2 h3 = -sum_J Z_J exactly (the cell
+    is neutral once the electrons are added).  Z defaults to 2 per atom."""
+    assert prob.bc == BC_PERIODIC and prob.atom_pos is not None
+    Z = np.full(prob.n_atoms, 2.0) if Z is None else np.asarray(Z, dtype=np.float64)
+    norm = (2.0 * np.pi * sigma * sigma) ** -1.5
+    L = [prob.n[a] * prob.h[a] for a in range(3)]
+    b = gaussian_potential(prob.n, prob.h, (0, 0, 0), prob.atom_pos, Z * norm, sigma,
+                           periodic_len=L)
+    h3 = float(np.prod(prob.h))
+    return b * (Z.sum() / (-b.sum() * h3))
+
+
 def small_problem(seed, n=(8, 8, 8), h=(0.6, 0.6, 0.6), fd_order=4, bc=BC_PERIODIC,
                   rcut=(2, 2, 2), order=12, kT=0.1, n_atoms=3, with_projectors=True, rc=1.3,
                   Ne=None):

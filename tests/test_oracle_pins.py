@@ -715,3 +715,87 @@ def test_cc_force_against_dense_evaluation(bc):
     assert hit > 0
     assert np.abs(f).max() > 1e-6
     assert np.abs(f - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------- #
+# SCF pieces: Poisson (Eq. (Poisson)), LDA exchange-correlation, mixing
+# --------------------------------------------------------------------------- #
+def _sparse_laplacian(n, h, r):
+    import scipy.sparse as sp
+    w = O.fd_weights(r)
+    mats = []
+    for a in range(3):
+        m = sp.lil_matrix((n[a], n[a]))
+        for i in range(n[a]):
+            m[i, i] += w[0]
+            for p in range(1, r + 1):
+                m[i, (i + p) % n[a]] += w[p]
+                m[i, (i - p) % n[a]] += w[p]
+        mats.append(m.tocsr() / (h[a] * h[a]))
+    I = [sp.identity(k, format="csr") for k in n]
+    # x fastest: kron(z, kron(y, x))
+    return (sp.kron(I[2], sp.kron(I[1], mats[0])) + sp.kron(I[2], sp.kron(mats[1], I[0]))
+            + sp.kron(mats[2], sp.kron(I[1], I[0])))
+
+
+@pytest.mark.parametrize("r", [1, 2, 6])
+def test_poisson_periodic_solves_the_sparse_fd_system(r):
+    """-Lap_h phi = 4 pi (f - mean f) with Lap_h assembled as a sparse matrix from the
+    FD weights (independent of the Fourier symbol), phi of zero mean."""
+    n, h = (9, 8, 14), (0.5, 0.6, 0.45)
+    rng = np.random.default_rng(r)
+    f = rng.standard_normal(int(np.prod(n)))
+    phi = O.poisson_periodic(f, n, h, r)
+    L = _sparse_laplacian(n, h, r)
+    res = -(L @ phi) - 4.0 * np.pi * (f - f.mean())
+    assert np.abs(res).max() <= 1e-10 * np.abs(f).max()
+    assert abs(phi.mean()) < 1e-12
+
+
+def test_lda_exchange_closed_form_and_potential_is_derivative():
+    """e_x = -(3/4)(9 / (4 pi^2))^(1/3) / rs = -0.4581652932831429 / rs, and
+    v_xc = d(n e_xc)/dn (central differences) for exchange plus correlation."""
+    n = np.geomspace(1e-4, 10.0, 41)
+    rs = np.cbrt(3.0 / (4.0 * np.pi * n))
+    exc, vxc = O.lda_pw92(n)
+    p = O.PW92
+    # the exchange part alone: remove correlation by its own definition at rs
+    sr = np.sqrt(rs)
+    q1 = 2 * p["A"] * (p["b1"] * sr + p["b2"] * rs + p["b3"] * rs * sr + p["b4"] * rs * rs)
+    ec = -2 * p["A"] * (1 + p["a1"] * rs) * np.log1p(1.0 / q1)
+    assert np.allclose(exc - ec, -0.4581652932831429 / rs, rtol=1e-13, atol=0)
+    d = 1e-5 * n
+    ep, _ = O.lda_pw92(n + d)
+    em, _ = O.lda_pw92(n - d)
+    dfd = ((n + d) * ep - (n - d) * em) / (2 * d)
+    assert np.allclose(vxc, dfd, rtol=1e-7, atol=0)
+    z, vz = O.lda_pw92(np.array([0.0, -1.0]))
+    assert np.all(z == 0) and np.all(vz == 0)
+
+
+def test_pw92_high_density_limit():
+    """As rs -> 0 the correlation energy grows like A ln rs with the exact
+    high-density (random-phase) coefficient A = (1 - ln 2) / pi^2."""
+    rs = np.array([1e-8, 1e-7])
+    n = 3.0 / (4.0 * np.pi * rs ** 3)
+    exc, _ = O.lda_pw92(n)
+    ec = exc + 0.4581652932831429 / rs
+    slope = (ec[1] - ec[0]) / np.log(rs[1] / rs[0])
+    assert abs(slope - (1.0 - np.log(2.0)) / np.pi ** 2) < 1e-4 * slope
+
+
+def test_scf_reaches_a_self_consistent_fixed_point():
+    """The oracle SCF (Anderson and plain linear mixing) converges to the same
+    fixed point: V_out(V) = V, N_e conserved at every iteration."""
+    p = synth.small_problem(3, n=(10, 10, 10), h=(0.6, 0.6, 0.6), n_atoms=3, rc=1.3, order=16,
+                            kT=0.1)
+    b = synth.pseudocharge(p)
+    V0 = np.zeros(p.V.size)
+    ra = O.scf(p, b, 6.0, V0, -8.0, 30.0, beta=0.3, tol=1e-8, max_iter=40)
+    rl = O.scf(p, b, 6.0, V0, -8.0, 30.0, beta=0.3, tol=1e-8, max_iter=200, anderson=False)
+    assert ra[-1]["residual"] < 1e-8 and rl[-1]["residual"] < 1e-8
+    assert len(ra) < len(rl)
+    for r in ra:
+        assert abs(r["rho"].sum() - 6.0) < 1e-8
+    assert np.abs(ra[-1]["V_out"] - rl[-1]["V_out"]).max() < 1e-7
+    assert np.abs(ra[-1]["V_out"] - ra[-1]["V_in"]).max() < 1e-7
