@@ -263,6 +263,59 @@ sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int
  * 27 (FP32): the box and the projector tables must share the LDS. */
 sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream);
 
+/* SCF outer loop on a periodic cell (Section 3's flowchart), every node of
+ * Omega a quadrature node (sq_setup with nodes == NULL):
+ *   V_in -> sq_density, sq_fermi_level (rho^q, lambda_f) -> n = rho^q / (h1 h2 h3)
+ *   -> phi of Eq. (Poisson), -Lap_h phi = 4 pi (n + b) with the FD Laplacian,
+ *      zero mean, by conjugate gradients warm-started from the last phi
+ *   -> V_out = phi + v_xc(n) (LDA: Slater exchange and the Perdew-Wang 1992
+ *      correlation, unpolarised) -> F = V_out - V_in
+ *   -> stop when RMS(F) < tol, else mix: V_in + beta F on the first step, then
+ *      Anderson with the previous pair, g = F.(F - F') / |F - F'|^2,
+ *      V_in <- (V_in - g (V_in - V')) + beta (F - g (F - F')).
+ * Periodic Poisson stands in for the paper's Dirichlet conditions from the
+ * surrounding crystal, and CG (the operator is symmetric positive definite on
+ * zero-mean functions) for its GMRES.  The loop synchronises the stream at
+ * every CG check and SCF test; the first call allocates 11 V-grid vectors of
+ * workspace. */
+typedef struct {
+    double beta;            /* mixing parameter (> 0)                                   */
+    double tol;             /* stop when the RMS of V_out - V_in is below tol (Ha)      */
+    double fermi_tol;       /* |N_e(lambda_f) - Ne| tolerance of every Fermi solve      */
+    double poisson_rtol;    /* CG stop: |residual| / |source| below this                */
+    int32_t max_iter;       /* SCF iterations (>= 1)                                    */
+    int32_t anderson;       /* 1: Anderson after the first step; 0: linear throughout   */
+    int32_t poisson_max_iter; /* CG steps per solve (>= 1)                              */
+    int32_t pad_;
+} sq_scf_params;
+
+typedef struct {
+    int32_t iterations;         /* SCF iterations run                                   */
+    int32_t converged;          /* 1 when RMS(V_out - V_in) < tol                       */
+    int32_t poisson_iterations; /* CG steps over all solves                             */
+    int32_t poisson_converged;  /* 1 when every solve reached poisson_rtol              */
+    double residual;            /* RMS(V_out - V_in) of the last iteration              */
+    double poisson_relres;      /* largest final relative CG residual                   */
+} sq_scf_info;
+
+/*   b         device [n_V] FP64 pseudocharge density of the nuclei (sum b h^3 = -Ne
+ *             for a neutral cell; its mean is removed with n's).
+ *   Ne        electron count of every Fermi solve.
+ *   lambda_min,
+ *   lambda_max  scaling bounds held for the whole loop (NaN, NaN: re-estimated on
+ *             the device at every iteration).
+ *   V         device [n_V] FP64: the starting V_in on entry; on return the last
+ *             V_in (the converged effective potential when info->converged).
+ *   rho       device [n_nodes] FP64 output: rho^q of the last iteration, or NULL.
+ *   lambda_f  device scalar FP64 output, or NULL.
+ *   info      host output.
+ * Errors: SQ_ERR_ARG for a non-periodic context, a node list, or bad params;
+ * SQ_ERR_NOT_CONVERGED from a Fermi solve; loop non-convergence is reported in
+ * info, not as an error. */
+sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, double lambda_max,
+                 const sq_scf_params *params, double *V, double *rho, double *lambda_f,
+                 sq_scf_info *info, void *stream);
+
 /* Synchronises the context's last stream and returns the device-side status
  * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */
 sq_status sq_device_status(sq_ctx *ctx);

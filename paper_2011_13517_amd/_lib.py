@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "SQ_OK", -1: "SQ_ERR_ARG", -2: "SQ_ERR_HIP", -3: "SQ_ERR_OOM"
 
 # every entry point declared in include/sq.h
 EXPORTS = ("sq_setup", "sq_destroy", "sq_last_error", "sq_get_info", "sq_density",
-           "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level", "sq_nonlocal_force",
+           "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level", "sq_nonlocal_force", "sq_scf",
            "sq_density_backward", "sq_device_status")
 
 
@@ -36,6 +36,18 @@ class sq_projectors(C.Structure):
     _fields_ = [("n_atoms", C.c_int32), ("n_proj", C.c_int32), ("sup_off", C.c_void_p),
                 ("sup_idx", C.c_void_p), ("chi", C.c_void_p), ("dchi", C.c_void_p),
                 ("c", C.c_void_p)]
+
+
+class sq_scf_params(C.Structure):
+    _fields_ = [("beta", C.c_double), ("tol", C.c_double), ("fermi_tol", C.c_double),
+                ("poisson_rtol", C.c_double), ("max_iter", C.c_int32), ("anderson", C.c_int32),
+                ("poisson_max_iter", C.c_int32), ("pad_", C.c_int32)]
+
+
+class sq_scf_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
+                ("poisson_iterations", C.c_int32), ("poisson_converged", C.c_int32),
+                ("residual", C.c_double), ("poisson_relres", C.c_double)]
 
 
 class sq_info(C.Structure):
@@ -85,6 +97,9 @@ def lib():
         L.sq_gauss_fermi_level.restype = C.c_int
         L.sq_nonlocal_force.argtypes = [VP, VP, VP]
         L.sq_nonlocal_force.restype = C.c_int
+        L.sq_scf.argtypes = [VP, VP, D, D, D, C.POINTER(sq_scf_params), VP, VP, VP,
+                             C.POINTER(sq_scf_info), VP]
+        L.sq_scf.restype = C.c_int
         L.sq_density_backward.argtypes = [VP, VP, VP, VP, VP, VP]
         L.sq_density_backward.restype = C.c_int
         L.sq_device_status.argtypes = [VP]
@@ -147,6 +162,13 @@ def sq_gauss_fermi_level(ctx, Ne, tol, max_iter, lf_ptr, rho_ptr, u_ptr, s_ptr, 
 
 def sq_nonlocal_force(ctx, f_ptr, stream):
     return check(lib().sq_nonlocal_force(ctx, f_ptr, stream))
+
+
+def sq_scf(ctx, b_ptr, Ne, lmin, lmax, params, V_ptr, rho_ptr, lf_ptr, stream):
+    info = sq_scf_info()
+    check(lib().sq_scf(ctx, b_ptr, Ne, lmin, lmax, C.byref(params), V_ptr, rho_ptr, lf_ptr,
+                       C.byref(info), stream))
+    return info
 
 
 def sq_density_backward(ctx, g_rho_ptr, g_u_ptr, dV_ptr, dR_ptr, stream):

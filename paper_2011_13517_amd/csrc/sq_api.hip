@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "sq_force.h"
+#include "sq_scf.h"
 #include "sq_kernels.h"
 
 using namespace sqk;
@@ -178,6 +179,10 @@ struct sq_ctx {
     Item *d_fitems = nullptr;
     std::vector<Group> fgroups;
     int64_t n_force_nodes = 0, force_region_points = 0;
+    // SCF loop: every node of Omega in linear order; workspace on first use
+    bool all_nodes = false;
+    double *d_scf = nullptr, *d_scf_part = nullptr, *d_scf_sc = nullptr;
+    double *d_scf_rho = nullptr, *d_scf_lf = nullptr;
     hipStream_t last_stream = nullptr;
 
     template <typename T>
@@ -493,6 +498,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     }
     if (n_nodes > INT32_MAX) return bail(fail(SQ_ERR_ARG, "too many nodes"));
     c.n_nodes = n_nodes;
+    c.all_nodes = nodes == nullptr && node_rcut == nullptr;
 
     // ---- work list -------------------------------------------------------
     std::vector<Item> items(n_nodes);
@@ -1112,6 +1118,90 @@ sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream) {
     };
     if (c.prec == SQ_FP64) TRY(launch(double{}));
     else TRY(launch(float{}));
+    c.last_stream = st;
+    return SQ_OK;
+}
+
+sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, double lambda_max,
+                 const sq_scf_params *sp, double *V, double *rho, double *lambda_f,
+                 sq_scf_info *info, void *stream) {
+    if (!ctx || !b || !sp || !V || !info) return fail(SQ_ERR_ARG, "NULL argument");
+    sq_ctx &c = *ctx;
+    if (!c.periodic) return fail(SQ_ERR_ARG, "sq_scf needs a periodic context");
+    if (!c.all_nodes) return fail(SQ_ERR_ARG, "sq_scf needs every node of the grid (nodes == NULL)");
+    if (!(sp->beta > 0.0) || !(sp->tol > 0.0) || !(sp->poisson_rtol > 0.0) ||
+        !(sp->fermi_tol >= 0.0) || sp->max_iter < 1 || sp->poisson_max_iter < 1 ||
+        (sp->anderson != 0 && sp->anderson != 1))
+        return fail(SQ_ERR_ARG, "invalid sq_scf_params");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nv = c.nv;
+    const int nb = N_PARTIAL;
+    // phi, n, src, r, p, Ap, V_out, F, the previous pair V' and F', and a vector of ones
+    constexpr int NVEC = 11;
+    if (!c.d_scf) {
+        TRY(c.alloc(&c.d_scf, (size_t)NVEC * nv));
+        TRY(c.alloc(&c.d_scf_part, 2 * (size_t)nb));
+        TRY(c.alloc(&c.d_scf_sc, (size_t)SC_COUNT));
+        TRY(c.alloc(&c.d_scf_rho, (size_t)c.n_nodes));
+        TRY(c.alloc(&c.d_scf_lf, 1));
+        HIP_TRY(k_fill_f64(c.d_scf, 0.0, (int64_t)(NVEC - 1) * nv, st));
+        HIP_TRY(k_fill_f64(c.d_scf + (NVEC - 1) * nv, 1.0, nv, st));
+    }
+    double *phi = c.d_scf, *nx = phi + nv, *src = nx + nv, *r = src + nv, *p = r + nv,
+           *Ap = p + nv, *vout = Ap + nv, *F = vout + nv, *Vp = F + nv, *Fp = Vp + nv,
+           *ones = Fp + nv;
+    ScfGrid g{};
+    for (int a = 0; a < 3; ++a) {
+        g.N[a] = c.N[a];
+        g.ih2[a] = c.ih2[a];
+    }
+    g.r = c.r;
+    for (int q = 0; q <= MAX_R; ++q) g.w[q] = c.w[q];
+    double *rhoq = rho ? rho : c.d_scf_rho;
+    double *lf = lambda_f ? lambda_f : c.d_scf_lf;
+    double *sc = c.d_scf_sc;
+    *info = sq_scf_info{};
+    info->poisson_converged = 1;
+    double hs[SC_COUNT];
+    auto fetch = [&](void) -> sq_status {
+        HIP_TRY(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SQ_OK;
+    };
+    const double inv_h3 = 1.0 / c.h3;
+    for (int it = 0; it < sp->max_iter; ++it) {
+        TRY(sq_density(ctx, V, lambda_min, lambda_max, nullptr, nullptr, stream));
+        TRY(sq_fermi_level(ctx, Ne, sp->fermi_tol, 200, lf, rhoq, nullptr, nullptr, stream));
+        HIP_TRY(scf_source(rhoq, b, nv, inv_h3, nx, src, ones, c.d_scf_part, nb, sc, st));
+        HIP_TRY(scf_cg_start(g, src, phi, r, p, c.d_scf_part, nb, sc, st));
+        int cgi = 0;
+        double relres = 0.0;
+        for (;;) {
+            TRY(fetch());
+            relres = hs[SC_BB] > 0.0 ? std::sqrt(std::max(hs[SC_RR], 0.0) / hs[SC_BB]) : 0.0;
+            if (relres < sp->poisson_rtol || cgi >= sp->poisson_max_iter) break;
+            const int chunk = std::min(10, sp->poisson_max_iter - cgi);
+            for (int j = 0; j < chunk; ++j)
+                HIP_TRY(scf_cg_iter(g, phi, r, p, Ap, c.d_scf_part, nb, sc, st));
+            cgi += chunk;
+        }
+        info->poisson_iterations += cgi;
+        info->poisson_relres = std::max(info->poisson_relres, relres);
+        if (!(relres < sp->poisson_rtol)) info->poisson_converged = 0;
+        HIP_TRY(scf_center(phi, nv, ones, c.d_scf_part, nb, sc, st));
+        HIP_TRY(scf_vout(phi, nx, V, vout, F, nv, c.d_scf_part, nb, sc, st));
+        TRY(fetch());
+        info->iterations = it + 1;
+        info->residual = std::sqrt(std::max(hs[SC_FF], 0.0) / (double)nv);
+        if (info->residual < sp->tol) {
+            info->converged = 1;
+            break;
+        }
+        if (it + 1 < sp->max_iter)   // V keeps the last V_in when the loop runs out
+            HIP_TRY(scf_mix(V, Vp, F, Fp, nv, sp->beta, sp->anderson && it > 0, c.d_scf_part,
+                            nb, sc, st));
+    }
+    TRY(sq_device_status(ctx));
     c.last_stream = st;
     return SQ_OK;
 }

@@ -181,6 +181,28 @@ class Context:
         L.sq_nonlocal_force(self.ctx, _ptr(f), _stream())
         return f[:self.n_atoms]
 
+    def scf(self, b: torch.Tensor, Ne: float, V: torch.Tensor, lambda_min: float = math.nan,
+            lambda_max: float = math.nan, beta: float = 0.3, tol: float = 1e-6,
+            fermi_tol: float = 1e-10, poisson_rtol: float = 1e-12, max_iter: int = 50,
+            anderson: bool = True, poisson_max_iter: int = 2000,
+            rho: Optional[torch.Tensor] = None, lambda_f: Optional[torch.Tensor] = None):
+        """sq_scf: runs the SCF loop in place on V (FP64, V grid); returns
+        (V, rho[n], lambda_f[1], info dict)."""
+        _dev(V)
+        _dev(b)
+        dev = V.device
+        if rho is None:
+            rho = torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
+        if lambda_f is None:
+            lambda_f = torch.zeros(1, dtype=torch.float64, device=dev)
+        p = L.sq_scf_params(beta=float(beta), tol=float(tol), fermi_tol=float(fermi_tol),
+                            poisson_rtol=float(poisson_rtol), max_iter=int(max_iter),
+                            anderson=int(bool(anderson)), poisson_max_iter=int(poisson_max_iter))
+        info = L.sq_scf(self.ctx, _ptr(b), float(Ne), float(lambda_min), float(lambda_max), p,
+                        _ptr(V), _ptr(rho), _ptr(lambda_f), _stream())
+        out = {k: getattr(info, k) for k, _ in L.sq_scf_info._fields_}
+        return V, rho, lambda_f, out
+
     def backward(self, g_rho: Optional[torch.Tensor], g_u: Optional[torch.Tensor],
                  dV: Optional[torch.Tensor] = None, dR: Optional[torch.Tensor] = None):
         """sq_density_backward: accumulates into dV (V grid) and dR [n_atoms, 3]."""
