@@ -117,6 +117,31 @@ def force_leg(ctx, prob, f_app, tot, lf, dev):
             "max_abs_f": float(f.abs().max().item())}
 
 
+def scf_leg(ctx, prob, tot, dev):
+    """Two iterations of the SCF loop (sq_scf) on the same cell from V_in = 0,
+    with the synthetic pseudocharge (Z = 2 per atom) and the scaling bounds of
+    the timed run widened by 5 Ha on each side; wall time per iteration (the
+    loop synchronises at every CG check)."""
+    import torch
+
+    from paper_2011_13517_amd import synth
+    b = torch.tensor(synth.pseudocharge(prob), dtype=torch.float64, device=dev)
+    Vs = torch.zeros(int(np.prod(prob.vshape)), dtype=torch.float64, device=dev)
+    om, tau = float(tot[4]), float(tot[5])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, lf, info = ctx.scf(b, 2.0 * prob.n_atoms, Vs, om - tau - 5.0, om + tau + 5.0,
+                             beta=0.3, tol=1e-6, max_iter=2, poisson_rtol=1e-10)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t
+    log(f"SCF: {info['iterations']} iterations, {t / info['iterations']:.3f} s each, "
+        f"residual {info['residual']:.3e}, {info['poisson_iterations']} CG steps")
+    return {"seconds_per_iteration": t / info["iterations"], "iterations": info["iterations"],
+            "residual": info["residual"], "poisson_cg_steps": info["poisson_iterations"],
+            "poisson_relres": info["poisson_relres"], "lambda_f": float(lf.item()),
+            "start": "V_in = 0, Gaussian pseudocharge Z = 2 per atom"}
+
+
 def gauss_leg(ctx, prob, V, tot, f_app, region_points, dev):
     """Gauss-quadrature density on the same workload and context: K Lanczos
     steps per node (sq_gauss_density: bounds as in the Chebyshev run, the
@@ -187,6 +212,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the Clenshaw-Curtis nonlocal-force leg")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF-loop leg")
     ap.add_argument("--no-gauss", action="store_true",
                     help="skip the Gauss-quadrature (LSSGQ) leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
@@ -315,6 +341,8 @@ def main():
         extra["cc_force"] = force_leg(ctx, prob, f_app, tot, lam_v.item(), dev)
     if not args.no_gauss:
         extra["lssgq"] = gauss_leg(ctx, prob, V, tot, f_app, region_points, dev)
+    if not args.no_scf and prob.bc == 0 and prob.nodes is None and prob.n_atoms:
+        extra["scf"] = scf_leg(ctx, prob, tot, dev)
     rho_np = rho.cpu().numpy()
     tot_om, tot_tau = float(tot[4]), float(tot[5])
     lmin, lmax = tot_om - tot_tau, tot_om + tot_tau
