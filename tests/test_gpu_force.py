@@ -107,3 +107,22 @@ def test_force_errors():
     with pytest.raises(SQError):        # no projectors
         ctx.nonlocal_force()
     ctx.close()
+
+
+def test_force_fp64_edge27_is_refused():
+    """FP64 regions of edge 27 have no column path (LDS): a clear SQ_ERR_ARG."""
+    from paper_2011_13517_amd import sq
+    from paper_2011_13517_amd._lib import SQError
+    prob = synth.config(2)
+    n = np.asarray(prob.n)
+    q = np.round(np.asarray(prob.atom_pos[0]) / np.asarray(prob.h)).astype(np.int64) % n
+    nodes = np.array([q[0] + n[0] * (q[1] + n[1] * q[2])], dtype=np.int64)   # inside atom 0
+    ctx = sq.Context(prob, precision=0, nodes=nodes)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    ctx.density(V, lmin, lmax)
+    ctx.fermi_level(max_iter=0, lambda_f=torch.zeros(1, dtype=torch.float64, device="cuda"),
+                    want_fields=False)
+    with pytest.raises(SQError, match="edges up to 21"):
+        ctx.nonlocal_force()
+    ctx.close()

@@ -199,3 +199,19 @@ def test_gauss_rules_integrate_gpu_moments():
         got = np.sum(g["w"] * np.cos(j * th), axis=1)
         assert np.abs(got - mu[:, j]).max() <= 1e-10, j
     assert np.abs(np.sum(g["w"] * np.cos(2 * K * th), axis=1) - mu[:, 2 * K]).max() > 1e-8
+
+
+def test_gauss_fp64_edge27_wave_per_atom_path():
+    """FP64 at edge 27: the box and the column tables do not share the LDS, so the
+    Lanczos sweep takes the wave-per-atom projector path; node by node against the
+    oracle on a subset of the 64^3 workload (K = 6)."""
+    print("[case] gauss fp64 edge 27", flush=True)
+    prob = dataclasses.replace(synth.config(2), order=6)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    rng = np.random.default_rng(21)
+    nodes = np.sort(rng.choice(prob.n_nodes, 24, replace=False)).astype(np.int64)
+    g = _gpu(prob, 0, lmin, lmax, nodes=nodes)
+    lam, w = O.gauss_rules(prob, lmin, lmax, prob.order, nodes=nodes)
+    tau = 0.5 * (lmax - lmin)
+    assert np.abs(g["lam"] - lam).max() <= 1e-10 * tau
+    assert np.abs(g["w"] - w).max() <= 1e-10
