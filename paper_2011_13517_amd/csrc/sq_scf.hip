@@ -4,7 +4,7 @@
 // exchange-correlation potential, and mixing of the effective potential.
 //
 // Every vector here lives on the V grid in FP64.  Reductions are deterministic
-// (fixed per-block partials, summed in block order by one thread), and the
+// (fixed per-block partials, summed in a fixed order by one wave), and the
 // scalars of the iteration stay on the device, so only the convergence tests
 // of the host loop synchronise.
 #include <cfloat>
@@ -38,11 +38,15 @@ __global__ void dot_partial_kernel(const double *x, const double *y, int64_t n, 
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// one wave: lane l sums partial[l], partial[l + 64], ... in order, then a fixed
+// butterfly (the same order on every run)
 __global__ void sum_finish_kernel(const double *partial, int nb, double *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int l = threadIdx.x;
     double t = 0.0;
-    for (int i = 0; i < nb; ++i) t += partial[i];
-    *out = t;
+    for (int i = l; i < nb; i += 64) t += partial[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (l == 0 && blockIdx.x == 0) *out = t;
 }
 
 // n = rho^q / (h1 h2 h3) and the Poisson source n + b
