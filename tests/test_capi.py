@@ -69,6 +69,17 @@ def test_null_arguments_rejected(lib):
     assert lib.sq_fermi_level(None, 1.0, 1e-8, 10, None, None, None, None, None) == L.SQ_ERR_ARG
     assert lib.sq_density_backward(None, None, None, None, None, None) == L.SQ_ERR_ARG
     assert lib.sq_get_info(None, None) == L.SQ_ERR_ARG
+    assert lib.sq_entropy(None, None, None, None) == L.SQ_ERR_ARG
+    assert lib.sq_gauss_density(None, None, 0.0, 1.0, None, None, None) == L.SQ_ERR_ARG
+    assert lib.sq_gauss_fermi_level(None, 1.0, 1e-8, 10, None, None, None, None, None,
+                                    None) == L.SQ_ERR_ARG
+    assert lib.sq_nonlocal_force(None, None, None) == L.SQ_ERR_ARG
+    sp = L.sq_scf_params(beta=0.3, tol=1e-6, fermi_tol=1e-10, poisson_rtol=1e-12, max_iter=5,
+                         anderson=1, poisson_max_iter=100)
+    info = L.sq_scf_info()
+    assert lib.sq_scf(None, None, 1.0, 0.0, 1.0, C.byref(sp), None, None, None, C.byref(info),
+                      None) == L.SQ_ERR_ARG
+    assert b"NULL" in lib.sq_last_error()
     assert lib.sq_destroy(None) == L.SQ_OK
 
 
