@@ -506,12 +506,17 @@ def scf(prob, b, Ne, V0, lmin, lmax, beta=0.3, tol=1e-6, max_iter=30, anderson=T
     V <- V + beta F; later steps are Anderson with one previous pair,
     g = F.(F - F') / |F - F'|^2, V <- (V - g (V - V')) + beta (F - g (F - F')).
     Stops when the RMS of F is below tol.  Every node of the periodic cell is a
-    quadrature node; (lmin, lmax) stay fixed.  Returns one record per iteration."""
+    quadrature node; (lmin, lmax) stay fixed, or with both None they are
+    re-estimated for every V_in by lanczos_bounds (100 steps, the 0x5EED start
+    vector, 1% margin).  Returns one record per iteration."""
     V = np.array(V0, np.float64)
+    fixed = lmin is not None
     h3 = float(np.prod(prob.h))
     Vp = Fp = None
     recs = []
     for it in range(max_iter):
+        if not fixed:
+            lmin, lmax = lanczos_bounds(prob, steps=100, seed=0x5EED, margin=0.01, V=V)
         mu = moments(prob, lmin, lmax, V=V)
         lf, _ = fermi_level(mu.sum(0), prob.kT, lmin, lmax, Ne, tol=fermi_tol)
         cg, _ = cheb_coeffs(KIND_G, lf, prob.kT, lmin, lmax, prob.order)

@@ -102,3 +102,20 @@ def test_scf_argument_errors():
     with pytest.raises(SQError):        # not periodic
         ctx.scf(b, 6.0, V, -8.0, 30.0)
     ctx.close()
+
+
+def test_scf_device_bounds_per_iteration():
+    """NaN bounds: the scaling is re-estimated on the device for every V_in (FP64
+    Lanczos, the oracle's start vector); three iterations against the oracle's
+    SCF with its own per-iteration estimate (the two estimates agree to ~1e-8)."""
+    print("[case] scf device bounds", flush=True)
+    prob = _problem()
+    b = synth.pseudocharge(prob)
+    ref = O.scf(prob, b, 6.0, np.zeros(prob.V.size), None, None, beta=0.3, tol=1e-14,
+                max_iter=3)
+    g = _gpu_scf(prob, b, 6.0, float("nan"), float("nan"), beta=0.3, tol=1e-14, max_iter=3,
+                 poisson_rtol=1e-13)
+    last = ref[-1]
+    assert g["info"]["iterations"] == 3
+    assert np.abs(g["V"] - last["V_in"]).max() <= 1e-6 * np.abs(last["V_in"]).max()
+    assert np.abs(g["rho"] - last["rho"]).max() <= 1e-6 * np.abs(last["rho"]).max()
