@@ -468,6 +468,47 @@ def poisson_periodic(f, n, h, r):
     return np.real(np.fft.ifftn(-4.0 * np.pi * F / L)).reshape(-1)
 
 
+def poisson_dirichlet(f, phi_bc, prob):
+    """phi on the padded grid Omega' of an embedded problem: -Lap_h phi = 4 pi f at
+    the nodes of Omega, phi = phi_bc on the padding (Dirichlet values from the
+    surrounding crystal; the padding must be at least the FD radius deep).  The
+    interior system is assembled as a sparse matrix and solved directly (a
+    library step)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    N, pad, n, r = prob.vshape, prob.pad, prob.n, prob.r
+    w = fd_weights(r)
+    mats = []
+    for a in range(3):
+        m = sp.lil_matrix((N[a], N[a]))
+        for i in range(N[a]):
+            m[i, i] += w[0]
+            for p in range(1, r + 1):
+                if i + p < N[a]:
+                    m[i, i + p] += w[p]
+                if i - p >= 0:
+                    m[i, i - p] += w[p]
+        mats.append(m.tocsr() / (prob.h[a] * prob.h[a]))
+    I = [sp.identity(k, format="csr") for k in N]
+    L = (sp.kron(I[2], sp.kron(I[1], mats[0])) + sp.kron(I[2], sp.kron(mats[1], I[0]))
+         + sp.kron(mats[2], sp.kron(I[1], I[0]))).tocsr()
+    zz, yy, xx = np.meshgrid(*(np.arange(k) for k in N[::-1]), indexing="ij")
+    inside = ((xx >= pad[0]) & (xx < pad[0] + n[0]) & (yy >= pad[1]) & (yy < pad[1] + n[1])
+              & (zz >= pad[2]) & (zz < pad[2] + n[2])).ravel()
+    ii, bb = np.flatnonzero(inside), np.flatnonzero(~inside)
+    phi = np.array(phi_bc, np.float64)
+    rhs = 4.0 * np.pi * np.asarray(f, np.float64)[ii] + L[ii][:, bb] @ phi[bb]
+    phi[ii] = spl.spsolve((-L[ii][:, ii]).tocsc(), rhs)
+    return phi
+
+
+def embed_nodes(prob):
+    """Linear indices on Omega' of the nodes of Omega (x fastest)."""
+    N, pad, n = prob.vshape, prob.pad, prob.n
+    zz, yy, xx = np.meshgrid(*(np.arange(k) for k in n[::-1]), indexing="ij")
+    return ((xx + pad[0]) + N[0] * ((yy + pad[1]) + N[1] * (zz + pad[2]))).ravel()
+
+
 PW92 = dict(A=0.031091, a1=0.21370, b1=7.5957, b2=3.5876, b3=1.6382, b4=0.49294)
 
 
@@ -498,7 +539,7 @@ def lda_pw92(n):
 
 
 def scf(prob, b, Ne, V0, lmin, lmax, beta=0.3, tol=1e-6, max_iter=30, anderson=True,
-        fermi_tol=1e-10):
+        fermi_tol=1e-10, phi_bc=None):
     """Fixed-point iteration on the effective potential (Section 3's flowchart):
     V_in -> moments (Eq. (Chebyshev)) -> lambda_f (Eq. (Ne)) -> rho^q (Eq. (rhoq))
     -> n = rho^q / (h1 h2 h3) -> phi of Eq. (Poisson) with source n + b -> V_out =
@@ -508,9 +549,17 @@ def scf(prob, b, Ne, V0, lmin, lmax, beta=0.3, tol=1e-6, max_iter=30, anderson=T
     Stops when the RMS of F is below tol.  Every node of the periodic cell is a
     quadrature node; (lmin, lmax) stay fixed, or with both None they are
     re-estimated for every V_in by lanczos_bounds (100 steps, the 0x5EED start
-    vector, 1% margin).  Returns one record per iteration."""
+    vector, 1% margin).  Embedded problems (V, b and phi_bc on Omega') solve the
+    Dirichlet problem of poisson_dirichlet with phi_bc on the padding and update
+    V only at the nodes of Omega (the padding keeps the surrounding crystal's
+    values); the RMS of F is over the nodes of Omega.  Returns one record per
+    iteration."""
     V = np.array(V0, np.float64)
     fixed = lmin is not None
+    emb = prob.bc == 2
+    if emb:
+        idx = embed_nodes(prob)
+        n_omega = idx.size
     h3 = float(np.prod(prob.h))
     Vp = Fp = None
     recs = []
@@ -521,12 +570,22 @@ def scf(prob, b, Ne, V0, lmin, lmax, beta=0.3, tol=1e-6, max_iter=30, anderson=T
         lf, _ = fermi_level(mu.sum(0), prob.kT, lmin, lmax, Ne, tol=fermi_tol)
         cg, _ = cheb_coeffs(KIND_G, lf, prob.kT, lmin, lmax, prob.order)
         rho_q, _ = contract(mu, cg, cg)
-        n_x = rho_q / h3
-        phi = poisson_periodic(n_x + b, prob.n, prob.h, prob.r)
-        _, vxc = lda_pw92(n_x)
-        Vout = phi + vxc
-        F = Vout - V
-        res = float(np.sqrt(np.mean(F * F)))
+        if emb:
+            n_x = np.zeros_like(V)
+            n_x[idx] = rho_q / h3
+            phi = poisson_dirichlet(n_x + b, phi_bc, prob)
+            _, vxc = lda_pw92(n_x)
+            Vout = V.copy()
+            Vout[idx] = phi[idx] + vxc[idx]
+            F = Vout - V
+            res = float(np.sqrt(np.sum(F * F) / n_omega))
+        else:
+            n_x = rho_q / h3
+            phi = poisson_periodic(n_x + b, prob.n, prob.h, prob.r)
+            _, vxc = lda_pw92(n_x)
+            Vout = phi + vxc
+            F = Vout - V
+            res = float(np.sqrt(np.mean(F * F)))
         recs.append(dict(V_in=V.copy(), V_out=Vout, rho=rho_q, lambda_f=lf, residual=res))
         if res < tol:
             break

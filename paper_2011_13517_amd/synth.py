@@ -383,13 +383,16 @@ def _config5(rng):
 
 
 def pseudocharge(prob: Problem, Z=None, sigma=1.0) -> np.ndarray:
-    """Seeded stand-in for the nuclei's pseudocharge density b(x) on a periodic
-    grid: a normalised Gaussian of charge -Z_J per atom (periodic images
-    summed), rescaled so that sum_x b(x) h1 h2 h3 = -sum_J Z_J exactly (the cell
-    is neutral once the electrons are added).  Z defaults to 2 per atom."""
-    assert prob.bc == BC_PERIODIC and prob.atom_pos is not None
+    """Seeded stand-in for the nuclei's pseudocharge density b(x): a normalised
+    Gaussian of charge -Z_J per atom.  Periodic grids sum the periodic images and
+    rescale so that sum_x b(x) h1 h2 h3 = -sum_J Z_J exactly (the cell is neutral
+    once the electrons are added); embedded grids give b on Omega' (no images,
+    no rescaling).  Z defaults to 2 per atom."""
+    assert prob.bc in (BC_PERIODIC, BC_EMBEDDED) and prob.atom_pos is not None
     Z = np.full(prob.n_atoms, 2.0) if Z is None else np.asarray(Z, dtype=np.float64)
     norm = (2.0 * np.pi * sigma * sigma) ** -1.5
+    if prob.bc == BC_EMBEDDED:
+        return gaussian_potential(prob.n, prob.h, prob.pad, prob.atom_pos, Z * norm, sigma)
     L = [prob.n[a] * prob.h[a] for a in range(3)]
     b = gaussian_potential(prob.n, prob.h, (0, 0, 0), prob.atom_pos, Z * norm, sigma,
                            periodic_len=L)
