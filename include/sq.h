@@ -263,19 +263,24 @@ sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int
  * 27 (FP32): the box and the projector tables must share the LDS. */
 sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream);
 
-/* SCF outer loop on a periodic cell (Section 3's flowchart), every node of
- * Omega a quadrature node (sq_setup with nodes == NULL):
+/* SCF outer loop (Section 3's flowchart) on a periodic cell or an embedded
+ * region, every node of Omega a quadrature node (sq_setup with nodes == NULL):
  *   V_in -> sq_density, sq_fermi_level (rho^q, lambda_f) -> n = rho^q / (h1 h2 h3)
- *   -> phi of Eq. (Poisson), -Lap_h phi = 4 pi (n + b) with the FD Laplacian,
- *      zero mean, by conjugate gradients warm-started from the last phi
+ *   -> phi of Eq. (Poisson), -Lap_h phi = 4 pi (n + b) with the FD Laplacian at
+ *      the nodes of Omega, by conjugate gradients: periodic cells remove the
+ *      source's mean and return phi of zero mean (warm-started from the last
+ *      phi); embedded regions hold phi = phi_bc on the padding of Omega' (the
+ *      paper's Dirichlet values from the surrounding crystal; the padding,
+ *      rcut, must be at least the FD radius deep) and start from phi_bc
  *   -> V_out = phi + v_xc(n) (LDA: Slater exchange and the Perdew-Wang 1992
- *      correlation, unpolarised) -> F = V_out - V_in
- *   -> stop when RMS(F) < tol, else mix: V_in + beta F on the first step, then
+ *      correlation, unpolarised) at the nodes of Omega; embedded regions keep
+ *      V_in on the padding -> F = V_out - V_in
+ *   -> stop when RMS(F) over the nodes of Omega < tol, else mix: V_in + beta F
+ *      on the first step, then
  *      Anderson with the previous pair, g = F.(F - F') / |F - F'|^2,
  *      V_in <- (V_in - g (V_in - V')) + beta (F - g (F - F')).
- * Periodic Poisson stands in for the paper's Dirichlet conditions from the
- * surrounding crystal, and CG (the operator is symmetric positive definite on
- * zero-mean functions) for its GMRES.  The loop synchronises the stream at
+ * CG (the operator is symmetric positive definite: on zero-mean functions for
+ * periodic cells) stands in for the paper's GMRES.  The loop synchronises the stream at
  * every CG check and SCF test; the first call allocates 11 V-grid vectors of
  * workspace. */
 typedef struct {
@@ -298,8 +303,11 @@ typedef struct {
     double poisson_relres;      /* largest final relative CG residual                   */
 } sq_scf_info;
 
-/*   b         device [n_V] FP64 pseudocharge density of the nuclei (sum b h^3 = -Ne
- *             for a neutral cell; its mean is removed with n's).
+/*   b         device [n_V] FP64 pseudocharge density of the nuclei on V's grid (a
+ *             periodic cell: sum b h^3 = -Ne for neutrality; its mean is removed
+ *             with n's).
+ *   phi_bc    device [n_V] FP64: embedded regions, the electrostatic potential
+ *             whose padding values are the Dirichlet data; NULL for periodic cells.
  *   Ne        electron count of every Fermi solve.
  *   lambda_min,
  *   lambda_max  scaling bounds held for the whole loop (NaN, NaN: re-estimated on
@@ -309,12 +317,13 @@ typedef struct {
  *   rho       device [n_nodes] FP64 output: rho^q of the last iteration, or NULL.
  *   lambda_f  device scalar FP64 output, or NULL.
  *   info      host output.
- * Errors: SQ_ERR_ARG for a non-periodic context, a node list, or bad params;
+ * Errors: SQ_ERR_ARG for a Dirichlet-clipped context, a node list, an embedded
+ * context without phi_bc or with padding shallower than the FD radius, or bad params;
  * SQ_ERR_NOT_CONVERGED from a Fermi solve; loop non-convergence is reported in
  * info, not as an error. */
-sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, double lambda_max,
-                 const sq_scf_params *params, double *V, double *rho, double *lambda_f,
-                 sq_scf_info *info, void *stream);
+sq_status sq_scf(sq_ctx *ctx, const double *b, const double *phi_bc, double Ne,
+                 double lambda_min, double lambda_max, const sq_scf_params *params, double *V,
+                 double *rho, double *lambda_f, sq_scf_info *info, void *stream);
 
 /* Synchronises the context's last stream and returns the device-side status
  * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */

@@ -97,7 +97,7 @@ def lib():
         L.sq_gauss_fermi_level.restype = C.c_int
         L.sq_nonlocal_force.argtypes = [VP, VP, VP]
         L.sq_nonlocal_force.restype = C.c_int
-        L.sq_scf.argtypes = [VP, VP, D, D, D, C.POINTER(sq_scf_params), VP, VP, VP,
+        L.sq_scf.argtypes = [VP, VP, VP, D, D, D, C.POINTER(sq_scf_params), VP, VP, VP,
                              C.POINTER(sq_scf_info), VP]
         L.sq_scf.restype = C.c_int
         L.sq_density_backward.argtypes = [VP, VP, VP, VP, VP, VP]
@@ -164,10 +164,10 @@ def sq_nonlocal_force(ctx, f_ptr, stream):
     return check(lib().sq_nonlocal_force(ctx, f_ptr, stream))
 
 
-def sq_scf(ctx, b_ptr, Ne, lmin, lmax, params, V_ptr, rho_ptr, lf_ptr, stream):
+def sq_scf(ctx, b_ptr, phi_bc_ptr, Ne, lmin, lmax, params, V_ptr, rho_ptr, lf_ptr, stream):
     info = sq_scf_info()
-    check(lib().sq_scf(ctx, b_ptr, Ne, lmin, lmax, C.byref(params), V_ptr, rho_ptr, lf_ptr,
-                       C.byref(info), stream))
+    check(lib().sq_scf(ctx, b_ptr, phi_bc_ptr, Ne, lmin, lmax, C.byref(params), V_ptr, rho_ptr,
+                       lf_ptr, C.byref(info), stream))
     return info
 
 

@@ -1122,12 +1122,20 @@ sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream) {
     return SQ_OK;
 }
 
-sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, double lambda_max,
-                 const sq_scf_params *sp, double *V, double *rho, double *lambda_f,
-                 sq_scf_info *info, void *stream) {
+sq_status sq_scf(sq_ctx *ctx, const double *b, const double *phi_bc, double Ne,
+                 double lambda_min, double lambda_max, const sq_scf_params *sp, double *V,
+                 double *rho, double *lambda_f, sq_scf_info *info, void *stream) {
     if (!ctx || !b || !sp || !V || !info) return fail(SQ_ERR_ARG, "NULL argument");
     sq_ctx &c = *ctx;
-    if (!c.periodic) return fail(SQ_ERR_ARG, "sq_scf needs a periodic context");
+    const bool emb = c.p.bc == SQ_BC_EMBEDDED;
+    if (!c.periodic && !emb)
+        return fail(SQ_ERR_ARG, "sq_scf needs a periodic or an embedded context");
+    if (emb && !phi_bc) return fail(SQ_ERR_ARG, "an embedded sq_scf needs phi_bc");
+    if (emb)
+        for (int a = 0; a < 3; ++a)
+            if (c.p.rcut[a] < c.r)
+                return fail(SQ_ERR_ARG, "an embedded sq_scf needs padding (rcut) >= the FD "
+                            "radius %d on every axis", c.r);
     if (!c.all_nodes) return fail(SQ_ERR_ARG, "sq_scf needs every node of the grid (nodes == NULL)");
     if (!(sp->beta > 0.0) || !(sp->tol > 0.0) || !(sp->poisson_rtol > 0.0) ||
         !(sp->fermi_tol >= 0.0) || sp->max_iter < 1 || sp->poisson_max_iter < 1 ||
@@ -1153,9 +1161,16 @@ sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, dou
     ScfGrid g{};
     for (int a = 0; a < 3; ++a) {
         g.N[a] = c.N[a];
+        g.n[a] = c.p.n[a];
+        g.pad[a] = emb ? c.p.rcut[a] : 0;
         g.ih2[a] = c.ih2[a];
     }
     g.r = c.r;
+    g.periodic = c.periodic;
+    const int64_t n_omega = (int64_t)c.p.n[0] * c.p.n[1] * c.p.n[2];
+    // the Dirichlet values of an embedded problem live on phi's padding (its
+    // interior starts from them too)
+    if (emb) HIP_TRY(hipMemcpyAsync(phi, phi_bc, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     for (int q = 0; q <= MAX_R; ++q) g.w[q] = c.w[q];
     double *rhoq = rho ? rho : c.d_scf_rho;
     double *lf = lambda_f ? lambda_f : c.d_scf_lf;
@@ -1172,7 +1187,7 @@ sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, dou
     for (int it = 0; it < sp->max_iter; ++it) {
         TRY(sq_density(ctx, V, lambda_min, lambda_max, nullptr, nullptr, stream));
         TRY(sq_fermi_level(ctx, Ne, sp->fermi_tol, 200, lf, rhoq, nullptr, nullptr, stream));
-        HIP_TRY(scf_source(rhoq, b, nv, inv_h3, nx, src, ones, c.d_scf_part, nb, sc, st));
+        HIP_TRY(scf_source(g, rhoq, b, inv_h3, nx, src, ones, c.d_scf_part, nb, sc, st));
         HIP_TRY(scf_cg_start(g, src, phi, r, p, c.d_scf_part, nb, sc, st));
         int cgi = 0;
         double relres = 0.0;
@@ -1188,11 +1203,11 @@ sq_status sq_scf(sq_ctx *ctx, const double *b, double Ne, double lambda_min, dou
         info->poisson_iterations += cgi;
         info->poisson_relres = std::max(info->poisson_relres, relres);
         if (!(relres < sp->poisson_rtol)) info->poisson_converged = 0;
-        HIP_TRY(scf_center(phi, nv, ones, c.d_scf_part, nb, sc, st));
-        HIP_TRY(scf_vout(phi, nx, V, vout, F, nv, c.d_scf_part, nb, sc, st));
+        if (!emb) HIP_TRY(scf_center(phi, nv, ones, c.d_scf_part, nb, sc, st));
+        HIP_TRY(scf_vout(g, phi, nx, V, vout, F, c.d_scf_part, nb, sc, st));
         TRY(fetch());
         info->iterations = it + 1;
-        info->residual = std::sqrt(std::max(hs[SC_FF], 0.0) / (double)nv);
+        info->residual = std::sqrt(std::max(hs[SC_FF], 0.0) / (double)n_omega);
         if (info->residual < sp->tol) {
             info->converged = 1;
             break;

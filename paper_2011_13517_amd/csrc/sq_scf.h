@@ -5,10 +5,15 @@
 
 namespace sqk {
 
-// periodic V grid and the FD Laplacian weights (w[0..r], Section 3)
+// V grid (Omega, or Omega' = Omega padded by pad[a] for embedded problems) and
+// the FD Laplacian weights (w[0..r], Section 3)
 struct ScfGrid {
     int32_t N[3];
+    int32_t n[3];       // Omega
+    int32_t pad[3];     // 0 for periodic grids
     int32_t r;
+    int32_t periodic;
+    int32_t pad_;
     double w[MAX_R + 1];
     double ih2[3];
 };
@@ -28,8 +33,9 @@ enum {
 
 hipError_t scf_dot(const double *x, const double *y, int64_t n, double *partial, int nb,
                    double *out, hipStream_t st);
-// nx = rho^q / h^3, src = 4 pi (nx + b - mean)
-hipError_t scf_source(const double *rho_q, const double *b, int64_t n, double inv_h3,
+// nx = rho^q / h^3 at the nodes of Omega (0 on the padding); src = 4 pi (nx + b),
+// made zero-mean on periodic grids, 0 on the padding
+hipError_t scf_source(const ScfGrid &g, const double *rho_q, const double *b, double inv_h3,
                       double *nx, double *src, const double *ones, double *partial, int nb,
                       double *sc, hipStream_t st);
 // r = src - A phi, p = r, rr, |src|^2 (A = -Lap_h)
@@ -39,9 +45,11 @@ hipError_t scf_cg_iter(const ScfGrid &g, double *phi, double *r, double *p, doub
                        double *partial, int nb, double *sc, hipStream_t st);
 hipError_t scf_center(double *x, int64_t n, const double *ones, double *partial, int nb,
                       double *sc, hipStream_t st);
-// V_out = phi + v_xc(nx), F = V_out - V_in, |F|^2
-hipError_t scf_vout(const double *phi, const double *nx, const double *vin, double *vout,
-                    double *F, int64_t n, double *partial, int nb, double *sc, hipStream_t st);
+// V_out = phi + v_xc(nx) at the nodes of Omega (V_in on the padding),
+// F = V_out - V_in, |F|^2
+hipError_t scf_vout(const ScfGrid &g, const double *phi, const double *nx, const double *vin,
+                    double *vout, double *F, double *partial, int nb, double *sc,
+                    hipStream_t st);
 hipError_t scf_mix(double *V, double *Vp, const double *F, double *Fp, int64_t n, double beta,
                    int anderson, double *partial, int nb, double *sc, hipStream_t st);
 

@@ -49,14 +49,25 @@ __global__ void sum_finish_kernel(const double *partial, int nb, double *out) {
     if (l == 0 && blockIdx.x == 0) *out = t;
 }
 
-// n = rho^q / (h1 h2 h3) and the Poisson source n + b
-__global__ void source_kernel(const double *rho_q, const double *b, int64_t n, double inv_h3,
+// the node of Omega at V-grid point i, or -1 on the padding
+__device__ __forceinline__ int64_t omega_index(const ScfGrid &g, int64_t i) {
+    const int x = (int)(i % g.N[0]) - g.pad[0];
+    const int y = (int)((i / g.N[0]) % g.N[1]) - g.pad[1];
+    const int z = (int)(i / ((int64_t)g.N[0] * g.N[1])) - g.pad[2];
+    if (x < 0 || y < 0 || z < 0 || x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) return -1;
+    return x + (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
+}
+
+// n = rho^q / (h1 h2 h3) and the Poisson source n + b at the nodes of Omega
+__global__ void source_kernel(ScfGrid g, const double *rho_q, const double *b, double inv_h3,
                               double *nx, double *src) {
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n;
+    const int64_t nv = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nv;
          i += (int64_t)gridDim.x * TPB) {
-        const double d = rho_q[i] * inv_h3;
+        const int64_t q = omega_index(g, i);
+        const double d = q >= 0 ? rho_q[q] * inv_h3 : 0.0;
         nx[i] = d;
-        src[i] = d + b[i];
+        src[i] = q >= 0 ? d + b[i] : 0.0;
     }
 }
 
@@ -68,7 +79,9 @@ __global__ void center_scale_kernel(double *x, int64_t n, const double *s, doubl
         x[i] = scale * (x[i] - m);
 }
 
-// y = -Lap_h x on the periodic grid: -sum_a (w_0 x + sum_p w_p (x_{+p} + x_{-p})) / h_a^2
+// y = -Lap_h x: -sum_a (w_0 x + sum_p w_p (x_{+p} + x_{-p})) / h_a^2, wrapped on
+// periodic grids; on embedded grids at the nodes of Omega only (the padding,
+// at least r deep, holds the Dirichlet values) and 0 on the padding
 __global__ void neg_lap_kernel(ScfGrid g, const double *x, double *y) {
     const int64_t nv = (int64_t)g.N[0] * g.N[1] * g.N[2];
     for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nv;
@@ -76,6 +89,10 @@ __global__ void neg_lap_kernel(ScfGrid g, const double *x, double *y) {
         const int ix = (int)(i % g.N[0]);
         const int iy = (int)((i / g.N[0]) % g.N[1]);
         const int iz = (int)(i / ((int64_t)g.N[0] * g.N[1]));
+        if (!g.periodic && omega_index(g, i) < 0) {
+            y[i] = 0.0;
+            continue;
+        }
         const int64_t sy = g.N[0], sz = (int64_t)g.N[0] * g.N[1];
         const double xc = x[i];
         double ax = g.w[0] * xc, ay = g.w[0] * xc, az = g.w[0] * xc;
@@ -131,6 +148,10 @@ __global__ void cg_direction_kernel(const double *sc, const double *r, double *p
         p[i] = r[i] + beta * p[i];
 }
 
+__global__ void zero_kernel(double *x) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *x = 0.0;
+}
+
 __global__ void cg_shift_kernel(double *sc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) sc[SC_RR] = sc[SC_RRN];
 }
@@ -152,12 +173,13 @@ __device__ __forceinline__ double vxc_pw92(double n) {
     return 4.0 / 3.0 * ex + ec - rs / 3.0 * dec;
 }
 
-// V_out = phi + v_xc(n);  F = V_out - V_in
-__global__ void vout_kernel(const double *phi, const double *nx, const double *vin, double *vout,
-                            double *F, int64_t n) {
+// V_out = phi + v_xc(n) at the nodes of Omega (V_in on the padding);  F = V_out - V_in
+__global__ void vout_kernel(ScfGrid g, const double *phi, const double *nx, const double *vin,
+                            double *vout, double *F) {
+    const int64_t n = (int64_t)g.N[0] * g.N[1] * g.N[2];
     for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * TPB) {
-        const double vo = phi[i] + vxc_pw92(nx[i]);
+        const double vo = omega_index(g, i) >= 0 ? phi[i] + vxc_pw92(nx[i]) : vin[i];
         vout[i] = vo;
         F[i] = vo - vin[i];
     }
@@ -216,12 +238,17 @@ hipError_t scf_dot(const double *x, const double *y, int64_t n, double *partial,
     return hipGetLastError();
 }
 
-hipError_t scf_source(const double *rho_q, const double *b, int64_t n, double inv_h3,
+hipError_t scf_source(const ScfGrid &g, const double *rho_q, const double *b, double inv_h3,
                       double *nx, double *src, const double *ones, double *partial, int nb,
                       double *sc, hipStream_t st) {
-    hipLaunchKernelGGL(source_kernel, dim3(nb), dim3(TPB), 0, st, rho_q, b, n, inv_h3, nx, src);
-    hipError_t e = scf_dot(src, ones, n, partial, nb, sc + SC_MEAN, st);
-    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    hipLaunchKernelGGL(source_kernel, dim3(nb), dim3(TPB), 0, st, g, rho_q, b, inv_h3, nx, src);
+    if (g.periodic) {   // the neutral cell: remove the mean
+        hipError_t e = scf_dot(src, ones, n, partial, nb, sc + SC_MEAN, st);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, sc + SC_MEAN);
+    }
     hipLaunchKernelGGL(center_scale_kernel, dim3(nb), dim3(TPB), 0, st, src, n,
                        (const double *)(sc + SC_MEAN), 4.0 * M_PI);
     return hipGetLastError();
@@ -262,9 +289,11 @@ hipError_t scf_center(double *x, int64_t n, const double *ones, double *partial,
     return hipGetLastError();
 }
 
-hipError_t scf_vout(const double *phi, const double *nx, const double *vin, double *vout,
-                    double *F, int64_t n, double *partial, int nb, double *sc, hipStream_t st) {
-    hipLaunchKernelGGL(vout_kernel, dim3(nb), dim3(TPB), 0, st, phi, nx, vin, vout, F, n);
+hipError_t scf_vout(const ScfGrid &g, const double *phi, const double *nx, const double *vin,
+                    double *vout, double *F, double *partial, int nb, double *sc,
+                    hipStream_t st) {
+    const int64_t n = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    hipLaunchKernelGGL(vout_kernel, dim3(nb), dim3(TPB), 0, st, g, phi, nx, vin, vout, F);
     return scf_dot(F, F, n, partial, nb, sc + SC_FF, st);
 }
 

@@ -185,11 +185,15 @@ class Context:
             lambda_max: float = math.nan, beta: float = 0.3, tol: float = 1e-6,
             fermi_tol: float = 1e-10, poisson_rtol: float = 1e-12, max_iter: int = 50,
             anderson: bool = True, poisson_max_iter: int = 2000,
-            rho: Optional[torch.Tensor] = None, lambda_f: Optional[torch.Tensor] = None):
-        """sq_scf: runs the SCF loop in place on V (FP64, V grid); returns
-        (V, rho[n], lambda_f[1], info dict)."""
+            rho: Optional[torch.Tensor] = None, lambda_f: Optional[torch.Tensor] = None,
+            phi_bc: Optional[torch.Tensor] = None):
+        """sq_scf: runs the SCF loop in place on V (FP64, V grid); phi_bc carries the
+        Dirichlet values of embedded regions.  Returns (V, rho[n], lambda_f[1],
+        info dict)."""
         _dev(V)
         _dev(b)
+        if phi_bc is not None:
+            _dev(phi_bc)
         dev = V.device
         if rho is None:
             rho = torch.empty(self.n_nodes, dtype=torch.float64, device=dev)
@@ -198,8 +202,8 @@ class Context:
         p = L.sq_scf_params(beta=float(beta), tol=float(tol), fermi_tol=float(fermi_tol),
                             poisson_rtol=float(poisson_rtol), max_iter=int(max_iter),
                             anderson=int(bool(anderson)), poisson_max_iter=int(poisson_max_iter))
-        info = L.sq_scf(self.ctx, _ptr(b), float(Ne), float(lambda_min), float(lambda_max), p,
-                        _ptr(V), _ptr(rho), _ptr(lambda_f), _stream())
+        info = L.sq_scf(self.ctx, _ptr(b), _ptr(phi_bc), float(Ne), float(lambda_min),
+                        float(lambda_max), p, _ptr(V), _ptr(rho), _ptr(lambda_f), _stream())
         out = {k: getattr(info, k) for k, _ in L.sq_scf_info._fields_}
         return V, rho, lambda_f, out
 

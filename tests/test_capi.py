@@ -77,8 +77,8 @@ def test_null_arguments_rejected(lib):
     sp = L.sq_scf_params(beta=0.3, tol=1e-6, fermi_tol=1e-10, poisson_rtol=1e-12, max_iter=5,
                          anderson=1, poisson_max_iter=100)
     info = L.sq_scf_info()
-    assert lib.sq_scf(None, None, 1.0, 0.0, 1.0, C.byref(sp), None, None, None, C.byref(info),
-                      None) == L.SQ_ERR_ARG
+    assert lib.sq_scf(None, None, None, 1.0, 0.0, 1.0, C.byref(sp), None, None, None,
+                      C.byref(info), None) == L.SQ_ERR_ARG
     assert b"NULL" in lib.sq_last_error()
     assert lib.sq_destroy(None) == L.SQ_OK
 
