@@ -259,8 +259,7 @@ sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int
  * the contraction and the accumulation are FP64.
  *   f_nl  device [n_atoms][3] FP64 output (overwritten).
  * Errors: SQ_ERR_STATE without sq_density and sq_fermi_level before it,
- * SQ_ERR_ARG without projectors or for regions of edge above 21 (FP64) or
- * 27 (FP32): the box and the projector tables must share the LDS. */
+ * SQ_ERR_ARG without projectors. */
 sq_status sq_nonlocal_force(sq_ctx *ctx, double *f_nl, void *stream);
 
 /* SCF outer loop (Section 3's flowchart) on a periodic cell or an embedded

@@ -17,7 +17,10 @@
 // it, the column path projects it onto every atom of the box (LDS atomics),
 // and the node's thread contracts the projections with the projector values
 // at the node and adds -4 h^3 c_Jl chi_Jlm(q) (chi_Jlm . d_a gamma) to the
-// atom's force with one FP64 atomic per atom and axis.
+// atom's force with one FP64 atomic per atom and axis.  Where the column
+// tables do not fit the LDS beside the box (FP64 at edge 27), the sweep and the
+// projections take the wave-per-atom path, and the lane that holds the node's
+// support row adds the node's term.
 #include "sq_force.h"
 #include "sq_region.h"
 
@@ -25,10 +28,16 @@ namespace sqk {
 
 // the column path fits the LDS for this precision and edge
 template <typename T, int E>
-constexpr bool force_supported() {
+constexpr bool force_colnl() {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
     constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
     return max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>() >= 32;
+}
+
+// the kernel exists: column path, or the wave-per-atom path with room for atoms
+template <typename T, int E>
+constexpr bool force_supported() {
+    return force_colnl<T, E>() || max_atoms_in_region<T, E, NP * (int)sizeof(T)>() > 0;
 }
 
 template <typename T, int E, int R, bool MASKZ>
@@ -36,22 +45,26 @@ __global__ void __launch_bounds__(((E * E + 63) / 64) * 64)
 cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
     constexpr int BLOCK = ((E * E + 63) / 64) * 64;
     constexpr int ZS = pencil_stride<T, E>();
+    constexpr int NW = BLOCK / 64;
     constexpr int COLBYTES = BLOCK * MAXC * (int)sizeof(ColEntry);
-    constexpr int MAXAT = max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>();
+    constexpr bool COLNL = force_colnl<T, E>();
+    constexpr int MAXAT = COLNL ? max_atoms_in_region<T, E, 2 * NP * (int)sizeof(T), COLBYTES>()
+                                : max_atoms_in_region<T, E, NP * (int)sizeof(T)>();
     constexpr int AT = MAXAT > 0 ? MAXAT : 1;
     // gamma takes E more VGPRs than the forward sweep: the diagonal is re-read
     // from L2 at the largest FP32 edge, and the stencil recomputes its neighbour
     // offsets per step (low-register variant), instead of spilling
     constexpr bool DREG = (sizeof(T) == 4 && E <= 21) || E <= 17;
-    constexpr bool LOWREG = E >= 27;
+    constexpr bool LOWREG = E >= 27 && COLNL;
     if constexpr (!force_supported<T, E>()) {
         return;
     } else {
     __shared__ __align__(16) T lds[region_lds_elems<T, E>()];
     __shared__ Slot slots[AT];
     __shared__ T pfac[AT][NP];
-    __shared__ T pacc[2][AT][NP];
-    __shared__ ColEntry colbuf[BLOCK * MAXC];
+    __shared__ T pacc[COLNL ? 2 : 1][COLNL ? AT : 1][NP];
+    __shared__ ColEntry colbuf[COLNL ? BLOCK * MAXC : 1];
+    __shared__ T dots[COLNL ? 1 : AT][NP];   // wave-per-atom path: raw projections
     __shared__ int s_item, s_nat;
 
     const int tid = threadIdx.x;
@@ -129,41 +142,52 @@ cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
         if (tid == 0 && s_nat > MAXAT) atomicOr(a.status, 1);
 
         ColNL<T> nl{};
-        for (int j = tid; j < c.nat; j += BLOCK) {
-            const double f = 2.0 * a.h3 / tau;
-            const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
+        if constexpr (COLNL) {
+            for (int j = tid; j < c.nat; j += BLOCK) {
+                const double f = 2.0 * a.h3 / tau;
+                const double *cj = a.cJ + (int64_t)slots[j].atom * NP;
 #pragma unroll
-            for (int l = 0; l < NP; ++l) {
-                pfac[j][l] = (T)(f * cj[l]);
-                pacc[0][j][l] = (T)0;
-                pacc[1][j][l] = (T)0;
+                for (int l = 0; l < NP; ++l) {
+                    pfac[j][l] = (T)(f * cj[l]);
+                    pacc[0][j][l] = (T)0;
+                    pacc[1][j][l] = (T)0;
+                }
             }
+            int ncol = build_columns<T>(a, slots, c.nat, c.active, px, py, c.dz,
+                                        colbuf + tid * MAXC);
+            if (ncol > MAXC) {
+                atomicOr(a.status, 2);
+                ncol = MAXC;
+            }
+            nl.cols = colbuf + tid * MAXC;
+            nl.ncol = ncol;
+            nl.pacc = &pacc[0][0][0];
+            nl.scale = &pfac[0][0];
+            nl.maxat = AT;
+            __syncthreads();
         }
-        int ncol = build_columns<T>(a, slots, c.nat, c.active, px, py, c.dz, colbuf + tid * MAXC);
-        if (ncol > MAXC) {
-            atomicOr(a.status, 2);
-            ncol = MAXC;
-        }
-        nl.cols = colbuf + tid * MAXC;
-        nl.ncol = ncol;
-        nl.pacc = &pacc[0][0][0];
-        nl.scale = &pfac[0][0];
-        nl.maxat = AT;
-        __syncthreads();
 
         // Chebyshev sweep (the newest vector alternates between v and w),
         // gamma += c'_k v_k after every step
         for (int k = 0; k < K; k += 2) {
-            region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
-                a, c, d, col, plane, gz0, n2, v, w, lds, nl, k == 0);
+            if constexpr (COLNL)
+                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
+                    a, c, d, col, plane, gz0, n2, v, w, lds, nl, k == 0);
+            else
+                region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, v, w, lds,
+                                                          slots, pfac, k == 0, tau);
             {
                 const T ck = (T)fp.cp[k + 1];
 #pragma unroll
                 for (int z = 0; z < E; ++z) g[z] += ck * w[z];
             }
             if (k + 1 < K) {
-                region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
-                    a, c, d, col, plane, gz0, n2, w, v, lds, nl, false);
+                if constexpr (COLNL)
+                    region_step_col<T, E, R, ZS, BLOCK, MASKZ, DREG, false, LOWREG>(
+                        a, c, d, col, plane, gz0, n2, w, v, lds, nl, false);
+                else
+                    region_step<T, E, R, ZS, NW, MASKZ, DREG>(a, c, d, col, plane, gz0, n2, w, v,
+                                                              lds, slots, pfac, false, tau);
                 const T ck = (T)fp.cp[k + 2];
 #pragma unroll
                 for (int z = 0; z < E; ++z) g[z] += ck * v[z];
@@ -207,6 +231,33 @@ cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
             __syncthreads();
             if (c.active) store_pencil<T, E, ZS>(c.mine, dg);
             __syncthreads();
+            if constexpr (!COLNL) {
+                // wave-per-atom path: raw projections of d_a gamma, then the lane
+                // holding the node's support row (if any) adds the node's term
+                if (c.nat)
+                    projector_dots<T, ZS, NW, false>(a, slots, pfac, dots, nullptr, lds, c.nat,
+                                                     c.dx, c.dy, c.dz, tau);
+                __syncthreads();
+                const int lane = tid & 63, wave = tid >> 6;
+                for (int j = wave; j < c.nat; j += NW) {
+                    const Slot sl = slots[j];
+                    for (int e = lane; e < sl.count; e += 64) {
+                        const int pk = a.sup_pack[sl.start + e];
+                        if (sl.ox + (pk & 1023) != it.ctr[0] ||
+                            sl.oy + ((pk >> 10) & 1023) != it.ctr[1] ||
+                            sl.oz + ((pk >> 20) & 1023) != cz0)
+                            continue;
+                        const T *chq = a.chi + (int64_t)(sl.start + e) * NP;
+                        const double *cj = a.cJ + (int64_t)sl.atom * NP;
+                        double f = 0.0;
+#pragma unroll
+                        for (int l = 0; l < NP; ++l)
+                            f += cj[l] * (double)chq[l] * (double)dots[j][l];
+                        atomicAdd(&fp.force[3 * sl.atom + ax], -4.0 * a.h3 * f);
+                    }
+                }
+                continue;
+            } else {
             if (c.nat) col_dots<T, false>(a, nl, c.mine);
             __syncthreads();
             if (is_ctr) {
@@ -226,6 +277,7 @@ cc_force_kernel(const RegionArgs<T> a, const ForceParams fp) {
             }
             __syncthreads();
             for (int i = tid; i < c.nat * NP; i += BLOCK) nl.pacc[(int64_t)nl.par * nl.maxat * NP + i] = (T)0;
+            }
         }
         __syncthreads();
     }

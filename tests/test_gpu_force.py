@@ -109,20 +109,22 @@ def test_force_errors():
     ctx.close()
 
 
-def test_force_fp64_edge27_is_refused():
-    """FP64 regions of edge 27 have no column path (LDS): a clear SQ_ERR_ARG."""
-    from paper_2011_13517_amd import sq
-    from paper_2011_13517_amd._lib import SQError
-    prob = synth.config(2)
+def test_force_fp64_edge27_wave_per_atom_path():
+    """FP64 regions of edge 27 have no room for the column tables: the force takes
+    the wave-per-atom projector path; 8 nodes around atom 0 of the 64^3 workload
+    (K = 30) against the oracle."""
+    print("[case] force fp64 edge 27", flush=True)
+    prob = dataclasses.replace(synth.config(2), order=30)
     n = np.asarray(prob.n)
-    q = np.round(np.asarray(prob.atom_pos[0]) / np.asarray(prob.h)).astype(np.int64) % n
-    nodes = np.array([q[0] + n[0] * (q[1] + n[1] * q[2])], dtype=np.int64)   # inside atom 0
-    ctx = sq.Context(prob, precision=0, nodes=nodes)
-    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    pos = np.asarray(prob.atom_pos[0]) / np.asarray(prob.h)
+    grid = np.stack(np.meshgrid(*(np.arange(k) for k in n), indexing="ij"), -1).reshape(-1, 3)
+    d = np.abs(grid - pos[None, :])
+    d = np.minimum(d, n[None, :] - d)
+    idx = np.argsort((d ** 2).sum(1))[:8]
+    nodes = np.sort(grid[idx, 0] + n[0] * (grid[idx, 1] + n[1] * grid[idx, 2])).astype(np.int64)
     lmin, lmax = O.lanczos_bounds(prob, steps=60)
-    ctx.density(V, lmin, lmax)
-    ctx.fermi_level(max_iter=0, lambda_f=torch.zeros(1, dtype=torch.float64, device="cuda"),
-                    want_fields=False)
-    with pytest.raises(SQError, match="edges up to 21"):
-        ctx.nonlocal_force()
-    ctx.close()
+    lf = 0.5 * (lmin + lmax) - 0.45 * (lmax - lmin)
+    f = _gpu_force(prob, 0, lmin, lmax, lf, nodes=nodes)
+    ref = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
+    assert np.abs(ref[0]).max() > 0
+    assert np.abs(f - ref).max() <= 1e-10 * np.abs(ref).max()
