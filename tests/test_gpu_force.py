@@ -128,3 +128,38 @@ def test_force_fp64_edge27_wave_per_atom_path():
     ref = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
     assert np.abs(ref[0]).max() > 0
     assert np.abs(f - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_force_and_gauss_embedded_config5_corner():
+    """Embedded 128^3 workload (V and projectors on the 154^3 padded grid,
+    K = 120): 10 nodes at a corner of Omega, whose regions reach into the padding
+    and whose supports include atoms of the surrounding crystal; the nonlocal
+    force in FP64 (the wave-per-atom path at edge 27; these corner nodes give a
+    tiny force, too small for an FP32 comparison relative to it) and the Gauss
+    rules (K = 20) in FP32 against the oracle."""
+    from paper_2011_13517_amd import sq
+    print("[case] config5 corner force + gauss", flush=True)
+    prob = synth.config(5)
+    lmin, lmax = O.gershgorin(prob)
+    n0, n1 = prob.n[0], prob.n[1]
+    nodes = np.array([i + n0 * (j + n1 * k) for i, j, k in
+                      ((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (2, 1, 0),
+                       (3, 2, 1), (2, 3, 2), (4, 4, 4), (5, 3, 6))], dtype=np.int64)
+    lf = 0.5 * (lmin + lmax) - 0.45 * (lmax - lmin)
+    f = _gpu_force(prob, 0, lmin, lmax, lf, nodes=nodes)
+    ref = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
+    assert np.abs(ref).max() > 0
+    assert np.abs(f - ref).max() <= 1e-10 * np.abs(ref).max()
+    pg = dataclasses.replace(prob, order=20)
+    ctx = sq.Context(pg, precision=1, nodes=nodes)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    lam, w = ctx.gauss_density(V, lmin, lmax)
+    torch.cuda.synchronize()
+    ctx.status()
+    lam, w = lam.cpu().numpy(), w.cpu().numpy()
+    ctx.close()
+    lam_o, w_o = O.gauss_rules(pg, lmin, lmax, 20, nodes=nodes)
+    rho_g, _, _ = O.gauss_fields(lam, w, lf, prob.kT)
+    rho_o, _, _ = O.gauss_fields(lam_o, w_o, lf, prob.kT)
+    assert np.abs(rho_g - rho_o).max() <= 1e-5 * max(np.abs(rho_o).max(), 1e-12)
+    assert np.abs(w.sum(1) - 1.0).max() < 1e-5
