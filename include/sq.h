@@ -169,6 +169,11 @@ sq_status sq_density(sq_ctx *ctx, const double *V, double lambda_min, double lam
  *             energy per node), or NULL.
  *   totals    device [8] FP64 output: {N_e, U, dN_e/dlambda_f, dU/dlambda_f,
  *             omega, tau, iterations, status} with status 0 or SQ_ERR_*.
+ * Device status (totals[7] and sq_device_status): SQ_ERR_NOT_CONVERGED when
+ * [lambda_min, lambda_max] does not bracket the target (lambda_f = NaN), or
+ * when the bisection stops at max_iter midpoints or at a 4-eps bracket
+ * without |N_e - target| < tol_Ne (lambda_f = the last estimate); every new
+ * solve starts from SQ_OK.
  * Requires a preceding sq_density on the same context. */
 sq_status sq_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
                          double *lambda_f, double *rho, double *u, double *totals,
@@ -241,6 +246,8 @@ sq_status sq_gauss_density(sq_ctx *ctx, const double *V, double lambda_min, doub
  *   rho, u, s      device [n_nodes] FP64 outputs, or NULL.
  *   totals         device [8] FP64 output: {N_e, U, S, U - kT S, omega, tau,
  *                  iterations, status}, or NULL.
+ * Device status as in sq_fermi_level (not bracketed, or stopped without
+ * |N_e - target| < tol_Ne: SQ_ERR_NOT_CONVERGED).
  * Requires a preceding sq_gauss_density on the same context. */
 sq_status sq_gauss_fermi_level(sq_ctx *ctx, double Ne_target, double tol_Ne, int32_t max_iter,
                                double *lambda_f, double *rho, double *u, double *s,

@@ -233,7 +233,10 @@ class NotBracketed(RuntimeError):
     pass
 
 
-def fermi_level(M, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
+def fermi_level(M, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200, with_status=False):
+    """Bisection of Eq. (Ne) on the moment sums M.  Returns (lambda_f, iterations),
+    plus a converged flag (|N_e(lambda_f) - Ne| < tol reached before a 4-ulp bracket
+    or max_iter midpoints) when with_status is set."""
     M = np.ascontiguousarray(M, np.float64)
     lf = np.zeros(1)
     it = np.zeros(1, np.int32)
@@ -242,6 +245,8 @@ def fermi_level(M, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
                                it.ctypes.data)
     if rc == -4:
         raise NotBracketed("electron count not bracketed by [lambda_min, lambda_max]")
+    if with_status:
+        return float(lf[0]), int(it[0]), rc == 0
     return float(lf[0]), int(it[0])
 
 
@@ -314,7 +319,8 @@ def gauss_fields(lam, wgt, lf, kT):
     return rho, u, s
 
 
-def gauss_fermi_level(lam, wgt, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
+def gauss_fermi_level(lam, wgt, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200,
+                      with_status=False):
     """Bisection of Eq. (Ne) with the Gauss rules: N_e(lambda_f) = 2 sum_q sum_k w g,
     on [lmin, lmax] with the same rule as fermi_level (mid = lo + (hi - lo)/2, lo =
     mid when N_e(mid) < target, stop at |N_e - target| < tol or a 4-ulp bracket)."""
@@ -324,10 +330,12 @@ def gauss_fermi_level(lam, wgt, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
         raise NotBracketed("electron count not bracketed by [lambda_min, lambda_max]")
     mid = lo + 0.5 * (hi - lo)
     it = 0
+    converged = False
     for it in range(1, max_iter + 1):
         mid = lo + 0.5 * (hi - lo)
         n_mid = ne(mid)
         if abs(n_mid - Ne) < tol:
+            converged = True
             break
         if n_mid < Ne:
             lo = mid
@@ -335,6 +343,8 @@ def gauss_fermi_level(lam, wgt, kT, lmin, lmax, Ne, tol=1e-10, max_iter=200):
             hi = mid
         if hi - lo < 4.0 * np.finfo(float).eps * max(abs(lo), abs(hi)):
             break
+    if with_status:
+        return mid, it, converged
     return mid, it
 
 

@@ -422,7 +422,8 @@ double orc_electron_count(const double *M, int K, double lambda_f, double kT,
 /* Fermi level, Eq. (Ne): bisection on [lmin, lmax] for N_e(lambda_f) = target.
  * mid = lo + (hi - lo)/2; N_e(mid) < target -> lo = mid, else hi = mid;
  * stop when |N_e(mid) - target| < tol or hi - lo < 4 eps max(|lo|, |hi|).
- * Returns 0, or -4 when the bracket does not hold the target. */
+ * Returns 0, 1 when it stops (4-ulp bracket, max_iter midpoints) without
+ * |N_e - target| < tol, or -4 when the bracket does not hold the target. */
 int orc_fermi_level(const double *M, int K, double kT, double lmin, double lmax,
                     double target, double tol, int max_iter, double *lambda_f, int *iters) {
     double lo = lmin, hi = lmax;
@@ -431,17 +432,19 @@ int orc_fermi_level(const double *M, int K, double kT, double lmin, double lmax,
     *iters = 0;
     if (nlo > target || nhi < target) { *lambda_f = NAN; return -4; }
     double mid = lo + 0.5 * (hi - lo);
+    int converged = 0;
     for (int it = 0; it < max_iter; ++it) {
         mid = lo + 0.5 * (hi - lo);
         const double ne = orc_electron_count(M, K, mid, kT, lmin, lmax);
         *iters = it + 1;
-        if (fabs(ne - target) < tol) break;
+        if (fabs(ne - target) < tol) { converged = 1; break; }
         if (ne < target) lo = mid; else hi = mid;
         const double big = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
         if (hi - lo < 4.0 * 2.220446049250313e-16 * big) { mid = lo + 0.5 * (hi - lo); break; }
     }
     *lambda_f = mid;
-    return 0;
+    /* 1: stopped (4-ulp bracket or max_iter midpoints) without |N_e - target| < tol */
+    return converged ? 0 : 1;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -577,6 +577,12 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         const int64_t nnz = proj->sup_off[proj->n_atoms];
         if (proj->sup_off[0] != 0 || nnz < 0 || nnz > INT32_MAX)
             return bail(fail(SQ_ERR_ARG, "bad sup_off"));
+        // the whole offset array is checked before any table is read: every
+        // atom's rows must lie inside [0, nnz]
+        for (int J = 0; J < proj->n_atoms; ++J)
+            if (proj->sup_off[J + 1] < proj->sup_off[J] || proj->sup_off[J + 1] > nnz)
+                return bail(fail(SQ_ERR_ARG, "sup_off not monotone within [0, %lld] at atom %d",
+                                 (long long)nnz, J));
         atoms.resize(c.n_atoms);
         chi64.assign(nnz * NP, 0.0);
         cJ.assign((size_t)c.n_atoms * NP, 0.0);

@@ -153,6 +153,7 @@ __global__ void gauss_fermi_init_kernel(Scalars *s, double Ne, double tol, int m
     s->iters = 0;
     s->max_iter = max_iter;
     s->done = 0;
+    s->status = SQ_OK;   // a new solve: no status from an earlier one survives
     if (max_iter == 0) {
         s->lambda_f = *lf_in;
         s->done = 1;
@@ -206,8 +207,13 @@ __global__ void gauss_eval_kernel(Scalars *s, const double *lam, const double *w
             return;
         }
         if (ne < s->ne_target) s->lo = x; else s->hi = x;
+        // a 4-ulp bracket or max_iter midpoints without |N_e - target| < tol:
+        // lambda_f keeps the last midpoint, flagged as not converged
         const double big = fmax(fabs(s->lo), fabs(s->hi));
-        if (s->hi - s->lo < 4.0 * DBL_EPSILON * big || s->iters >= s->max_iter) s->done = 1;
+        if (s->hi - s->lo < 4.0 * DBL_EPSILON * big || s->iters >= s->max_iter) {
+            s->done = 1;
+            s->status = SQ_ERR_NOT_CONVERGED;
+        }
     }
 }
 

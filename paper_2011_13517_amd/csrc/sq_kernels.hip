@@ -318,6 +318,7 @@ __global__ void fermi_init_kernel(Scalars *s, double kT, int K, double Ne, doubl
     int l2 = 10;
     while ((double)(1LL << l2) < need && l2 < nq_cap_log2) ++l2;
     s->nq_log2 = l2;
+    s->status = SQ_OK;   // a new solve: no status from an earlier one survives
     if ((double)(1LL << l2) < need) s->status = SQ_ERR_ARG;
     s->lo = s->lmin;
     s->hi = s->lmax;
@@ -390,13 +391,17 @@ __global__ void fermi_eval_kernel(Scalars *s, const double *P, double kT, int ph
             return;
         }
         if (ne < s->ne_target) s->lo = lam; else s->hi = lam;
+        // a 4-ulp bracket or max_iter midpoints without |N_e - target| < tol:
+        // the estimate is returned, flagged as not converged
         const double big = fmax(fabs(s->lo), fabs(s->hi));
         if (s->hi - s->lo < 4.0 * DBL_EPSILON * big) {
             s->lambda_f = s->lo + 0.5 * (s->hi - s->lo);
             s->done = 1;
+            s->status = SQ_ERR_NOT_CONVERGED;
         } else if (s->iters >= s->max_iter) {
             s->lambda_f = lam;
             s->done = 1;
+            s->status = SQ_ERR_NOT_CONVERGED;
         }
     }
 }

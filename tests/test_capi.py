@@ -114,3 +114,23 @@ def _struct_fields(name):
 def test_binding_struct_layout_matches_header(name, cls):
     """The ctypes structures list the header's fields in the header's order."""
     assert _struct_fields(name) == [f[0] for f in cls._fields_]
+
+
+@pytest.mark.parametrize("sup_off", [[0, 100, 50], [0, 3, 2], [0, 5, 4], [1, 2, 3], [0, -1, 2]])
+def test_malformed_support_offsets_rejected(lib, sup_off):
+    """A projector CSR whose offsets run backwards, past nnz = sup_off[-1] or do
+    not start at 0 is refused with SQ_ERR_ARG before any table is read (the
+    support arrays below hold only nnz rows, so a read past them would be out of
+    bounds)."""
+    off = np.asarray(sup_off, np.int64)
+    nnz = max(int(off[-1]), 0)
+    idx = np.zeros(nnz, np.int64)
+    chi = np.zeros((nnz, 4))
+    c = np.ones((2, 4))
+    pr = L.sq_projectors(n_atoms=2, n_proj=4, sup_off=off.ctypes.data, sup_idx=idx.ctypes.data,
+                         chi=chi.ctypes.data, dchi=None, c=c.ctypes.data)
+    ctx = C.c_void_p()
+    st = lib.sq_setup(C.byref(_params()), C.byref(pr), None, None, 512, C.byref(ctx))
+    assert st == L.SQ_ERR_ARG
+    assert ctx.value is None
+    assert b"sup_off" in lib.sq_last_error()

@@ -226,6 +226,38 @@ def test_fermi_not_bracketed_reports_status():
     ctx.close()
 
 
+def test_fermi_max_iter_exhausted_reports_not_converged():
+    """A bisection cut off after 3 midpoints (|N_e - target| still above tol)
+    returns the oracle's third midpoint with status SQ_ERR_NOT_CONVERGED in
+    totals[7] and in sq_device_status; a following solve with room to converge
+    on the same moments reports SQ_OK again."""
+    print("[case] max_iter exhausted", flush=True)
+    sq = _sq()
+    prob = synth.small_problem(45, n=(8, 8, 8), rcut=(2, 2, 2), order=16, kT=0.1,
+                               with_projectors=False)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    mu_ref = O.moments(prob, lmin, lmax)
+    Ne = 0.4 * mu_ref.shape[0]
+    lf_o, it_o, conv_o = O.fermi_level(mu_ref.sum(0), prob.kT, lmin, lmax, Ne, tol=1e-12,
+                                       max_iter=3, with_status=True)
+    assert not conv_o and it_o == 3
+    ctx = sq.Context(prob, precision=0)
+    V = torch.tensor(prob.V, dtype=torch.float64, device="cuda")
+    ctx.density(V, lmin, lmax)
+    lam, _, _, tot = ctx.fermi_level(Ne=Ne, tol=1e-12, max_iter=3)
+    torch.cuda.synchronize()
+    assert tot[7].item() == -4 and tot[6].item() == 3
+    assert abs(lam.item() - lf_o) < 1e-12 * (lmax - lmin)
+    from paper_2011_13517_amd._lib import SQError
+    with pytest.raises(SQError):
+        ctx.status()
+    lam, _, _, tot = ctx.fermi_level(Ne=Ne, tol=1e-9, max_iter=200)
+    torch.cuda.synchronize()
+    ctx.status()
+    assert tot[7].item() == 0 and abs(tot[0].item() - Ne) < 1e-9
+    ctx.close()
+
+
 def test_edge_cases_single_node_and_thin_boxes():
     """K = 1, a single node, zero-width axes and anisotropic spacing."""
     print("[case] edge cases", flush=True)
@@ -271,7 +303,9 @@ def test_config5_embedded_full_fp32_sampled():
     assert np.abs(mu_s - mu_ref).max() < fp32_mu_tol(prob.order)
     rho_ref, _ = oracle_fields(mu_ref, lf, prob.kT, lmin, lmax, prob.order)
     assert np.abs(rho_all[sample] - rho_ref).max() / np.abs(rho_all).max() < 1e-5
-    assert abs(tot[0] - prob.Ne) < 1e-8 * prob.Ne
+    # the config's bisection tolerance, absolute: |N_e(lambda_f) - N_e| < 1e-8
+    assert abs(tot[0] - prob.Ne) < 1e-8, tot[0] - prob.Ne
+    assert tot[7] == 0
     assert abs(rho_all.sum() - prob.Ne) < 1e-6 * prob.Ne
 
 

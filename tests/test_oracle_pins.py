@@ -820,3 +820,134 @@ def test_poisson_dirichlet_recovers_a_manufactured_solution():
     f = -lap.ravel() / (4.0 * np.pi)      # only Omega's entries are used (no wrap reaches them)
     got = O.poisson_dirichlet(f, phi.ravel(), prob)
     assert np.abs(got - phi.ravel()).max() < 1e-10
+
+
+# --------------------------------------------------------------------------- #
+# PW92 correlation against its published asymptotic expansions
+# --------------------------------------------------------------------------- #
+def _pw92_correlation(rs):
+    """e_c(rs) of the oracle: e_xc minus the Slater exchange closed form, whose
+    constant is pinned above; rs is kept in [1e-5, 1e8] where the subtraction
+    loses at most ~1e-11 of e_c."""
+    rs = np.asarray(rs, np.float64)
+    exc, _ = O.lda_pw92(3.0 / (4.0 * np.pi * rs ** 3))
+    return exc + 0.4581652932831429 / rs
+
+
+def _lsq(cols, y):
+    M = np.stack(cols, 1)
+    s = np.abs(M).max(0)
+    return np.linalg.lstsq(M / s, y, rcond=None)[0] / s
+
+
+def test_pw92_high_density_expansion_coefficients():
+    """For rs -> 0 the unpolarised correlation energy of Perdew & Wang (1992) has
+    the expansion e_c = c0 ln rs - c1 + c2 rs ln rs - c3 rs + ..., with the
+    published c0 = (1 - ln 2) / pi^2 (the random-phase value), c1 = 0.046644,
+    c2 = 0.00664 and c3 = 0.01043, and no sqrt(rs) term.  The fit reproduces them
+    through its parameters: c0 = A, c1 = -2A ln(2 A beta1) (beta1), no sqrt(rs)
+    term iff beta2 = 2 A beta1^2 (beta2), c2 = A alpha1 (alpha1), and c3 through
+    beta3 with the others.  A 1% change of any of these parameters moves one of
+    the fitted coefficients below by at least 10x its tolerance."""
+    rs = np.geomspace(1e-5, 1e-3, 60)
+    co = _lsq([np.ones_like(rs), np.log(rs), np.sqrt(rs), rs * np.log(rs), rs,
+               rs ** 1.5 * np.log(rs), rs ** 1.5], _pw92_correlation(rs))
+    const, c0, b_half, c2, c3 = co[0], co[1], co[2], co[3], -co[4]
+    assert abs(c0 - (1.0 - np.log(2.0)) / np.pi ** 2) < 2e-6, c0
+    assert abs(-const - 0.046644) < 3e-6, const
+    assert abs(b_half) < 2e-5, b_half
+    assert abs(c2 - 0.00664) < 1.5e-5, c2
+    assert abs(c3 - 0.01043) < 1e-4, c3
+
+
+def test_pw92_low_density_expansion_coefficients():
+    """For rs -> infinity, e_c = -d0 / rs + d1 / rs^(3/2) + ... with the published
+    d0 = 0.4335 and d1 = 1.4408 (the fit gives d0 = alpha1 / beta4 and
+    d1 = alpha1 beta3 / beta4^2, so this pins beta4 and beta3)."""
+    rs = np.geomspace(1e4, 1e8, 60)
+    co = _lsq([1.0 / rs, rs ** -1.5, rs ** -2.0, rs ** -2.5], _pw92_correlation(rs))
+    assert abs(-co[0] - 0.4335) < 1e-4, co[0]
+    assert abs(co[1] - 1.4408) < 3e-4, co[1]
+
+
+# --------------------------------------------------------------------------- #
+# Clenshaw-Curtis force against the adjoint: the full-trace identity
+# --------------------------------------------------------------------------- #
+def _box_gradient_matrix(n, h, r, axis):
+    """Central first-derivative stencil of radius r along `axis` on the whole
+    n-grid with zero outside it, as a dense matrix (x fastest); it is
+    antisymmetric, which is all the identity below needs."""
+    wp = O.fd_first_weights(r)
+    D1 = np.zeros((n[axis], n[axis]))
+    for i in range(n[axis]):
+        for p in range(1, r + 1):
+            if i + p < n[axis]:
+                D1[i, i + p] += wp[p] / h[axis]
+            if i - p >= 0:
+                D1[i, i - p] -= wp[p] / h[axis]
+    mats = [np.eye(n[2]), np.eye(n[1]), np.eye(n[0])]
+    mats[2 - axis] = D1
+    return np.kron(np.kron(mats[0], mats[1]), mats[2])
+
+
+def test_cc_force_equals_minus_grand_potential_gradient_full_trace():
+    """Eq. (NLforceSQ) is the derivative of the band grand potential.  In the
+    full-trace limit (every node's region is the whole Dirichlet domain, so all
+    node Hamiltonians are the same Hs and gamma = p(Hs) is symmetric):
+      Omega = 2 tr P(H) with P' = p the degree-K Chebyshev series of the Fermi
+      function, and dOmega/dR_J = 2 tr[p(H) dV_J/dR_J].
+    With dchi/dR_J := -D chi (D the antisymmetric FD gradient on the domain, the
+    discrete counterpart of dchi(x - R)/dR = -grad chi), summation by parts turns
+    this into 4 h^3 sum_lm c chi^T D gamma chi, which is minus the paper's force
+    -4 sum_q e_q^T V_J D gamma e_q.  The two sides come from different oracle
+    routines: cc_nonlocal_force (numpy recurrence per node, box gradient of
+    gamma, projections) and adjoint (the C reverse recurrence fed the Chebyshev
+    coefficients of the antiderivative P, through the dchi table).  A wrong sign,
+    a missing factor 2 or a transposed gradient in either breaks the equality."""
+    prob = synth.small_problem(71, n=(7, 6, 8), h=(0.55, 0.6, 0.5), bc=synth.BC_DIRICHLET,
+                               rcut=(8, 8, 8), n_atoms=3, rc=1.3, order=16, kT=0.25,
+                               fd_order=4)
+    N = prob.vshape
+    nv = int(np.prod(N))
+    # dchi := -D chi on every grid point where it is nonzero (supports widened)
+    chi_full = np.zeros((prob.n_atoms, prob.n_proj, nv))
+    for J in range(prob.n_atoms):
+        for s in range(prob.sup_off[J], prob.sup_off[J + 1]):
+            chi_full[J, :, prob.sup_idx[s]] += prob.chi[s]
+    Ds = [_box_gradient_matrix(N, prob.h, prob.r, a) for a in range(3)]
+    off, idx, chi, dchi = [0], [], [], []
+    for J in range(prob.n_atoms):
+        g = np.stack([-(Ds[a] @ chi_full[J].T).T for a in range(3)], -1)   # [n_proj, nv, 3]
+        pts = np.flatnonzero(np.any(chi_full[J] != 0, 0) | np.any(g != 0, (0, 2)))
+        idx.append(pts)
+        chi.append(chi_full[J][:, pts].T)
+        dchi.append(np.transpose(g[:, pts, :], (1, 0, 2)))
+        off.append(off[-1] + pts.size)
+    import dataclasses
+    p2 = dataclasses.replace(prob, sup_off=np.array(off, np.int64),
+                             sup_idx=np.concatenate(idx).astype(np.int64),
+                             chi=np.concatenate(chi), dchi=np.concatenate(dchi))
+    lmin, lmax = _bounds(p2)
+    tau = 0.5 * (lmax - lmin)
+    lf = 0.5 * (lmin + lmax) - 0.25 * (lmax - lmin)
+    K = prob.order
+    # every node's box is the whole domain
+    _, dims, _ = O.node_box(p2, 0, p2.rcut)
+    assert tuple(dims) == tuple(N)
+    f_cc = O.cc_nonlocal_force(p2, lmin, lmax, lf)
+    # antiderivative of p = c_0/2 + sum c_k T_k: C_k = (c_{k-1} - c_{k+1}) / (2k), k = 1..K+1
+    c, _ = O.cheb_coeffs(O.KIND_G, lf, prob.kT, lmin, lmax, K)
+    cc = np.concatenate([c, [0.0, 0.0]])
+    C = np.zeros(K + 2)
+    for k in range(1, K + 2):
+        C[k] = (cc[k - 1] - cc[k + 1]) / (2.0 * k)
+    # the integral identity behind the coefficients (an independent numpy check)
+    x = np.linspace(-0.9, 0.9, 7)
+    pd = npcheb.chebval(x, npcheb.chebder(C))
+    pg = npcheb.chebval(x, np.concatenate([[0.5 * c[0]], c[1:]]))
+    assert np.abs(pd - pg).max() < 1e-13
+    # y = Omega = 2 sum_q e_q^T tau P(Hs) e_q: d/dR at fixed omega, tau
+    a = np.tile(2.0 * tau * C, (p2.n_nodes, 1))
+    _, dR = O.adjoint(p2, lmin, lmax, a)
+    assert np.abs(f_cc).max() > 1e-4
+    assert np.abs(f_cc + dR).max() <= 1e-11 * np.abs(f_cc).max(), np.abs(f_cc + dR).max()
