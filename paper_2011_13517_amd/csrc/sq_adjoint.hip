@@ -21,9 +21,9 @@ static hipError_t dispatch(int prec, int E, int R, bool M, bool G, const void *a
     }
 }
 
-// FP32 adjoint up to edge 27, FP64 adjoint up to edge 21 (LDS holds the box
-// plus the per-atom projection tables).
-int adjoint_max_edge(int prec) { return prec == SQ_FP64 ? 21 : 27; }
+// Edge 27 in FP64 runs its own kernel (sq_adjoint64.hip); the kernels here
+// cover FP64 up to edge 21 and FP32 up to edge 27.
+int adjoint_max_edge(int prec) { return 27; }
 
 hipError_t launch_adjoint(int prec, int E, int R, bool storeall, bool grad, const void *args,
                           int grid, hipStream_t s) {

@@ -841,8 +841,12 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     if (c.adj_ok) {
         const bool grad = c.n_atoms > 0 && c.have_dchi;
         const int64_t esz = c.aprec == SQ_FP64 ? 8 : 4;
+        // groups of the FP64 edge-27 kernel keep v_k, vt_{k+1}, the forward
+        // projections and the atom list of their in-flight regions (own layout)
+        auto zc = [&](const Group &g) { return adjoint64_edge(c.aprec, g.E); };
         auto agrid = [&](const Group &g, bool sa) {
-            const int occ = adjoint_blocks_per_cu(c.aprec, g.E, c.r, sa, grad);
+            const int occ = zc(g) ? adjoint64_blocks_per_cu(g.E, c.r, grad)
+                                  : adjoint_blocks_per_cu(c.aprec, g.E, c.r, sa, grad);
             return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
         };
         // stride 1 keeps every v_k of the in-flight regions (no rebuild, two
@@ -850,8 +854,9 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         // stays below 8 GiB
         int64_t pool_sa = 0;
         for (const Group &g : c.groups)
-            pool_sa = std::max<int64_t>(pool_sa, (int64_t)agrid(g, true) *
-                                                     storeall_slot_elems(c.K, g.E) * esz);
+            if (!zc(g))
+                pool_sa = std::max<int64_t>(pool_sa, (int64_t)agrid(g, true) *
+                                                         storeall_slot_elems(c.K, g.E) * esz);
         c.storeall = params->ckpt_every == 1 ||
                      (params->ckpt_every == 0 && pool_sa <= (int64_t)8 << 30);
         // a store-all kernel without the column projector path (never the case
@@ -868,6 +873,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
             // rebuild layout, so a store-all slot also covers that one
             int64_t st = (int64_t)c.n_ckpt * 2 * e3;
             if (c.storeall) st = std::max<int64_t>(st, storeall_slot_elems(c.K, g.E));
+            if (zc(g)) st = adjoint64_slot_elems(c.K, g.E);
             c.ckpt_stride = std::max(c.ckpt_stride, st);
         }
         c.ckpt_stride = round_np(c.ckpt_stride);   // slots stay NP-vector aligned
@@ -997,7 +1003,10 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
             a.ckpt_every = c.p.ckpt_every;
             a.n_ckpt = c.n_ckpt;
             a.ckpt_stride = c.ckpt_stride;
-            HIP_TRY(launch_adjoint(c.aprec, gr.E, c.r, c.storeall, grad, &a, gr.grid_adj, st));
+            if (adjoint64_edge(c.aprec, gr.E))
+                HIP_TRY(launch_adjoint64(gr.E, c.r, grad, &a, gr.grid_adj, st));
+            else
+                HIP_TRY(launch_adjoint(c.aprec, gr.E, c.r, c.storeall, grad, &a, gr.grid_adj, st));
         }
         return SQ_OK;
     };

@@ -1,13 +1,16 @@
 """Adjoint (sq_density_backward) through the C ABI against the FP64 oracle.
 
 Tolerances: the FP64 adjoint (the default adjoint_precision, also behind an FP32
-forward context) within 1e-10 max-norm relative of the oracle.  The FP32 adjoint
-(FP32 primal and adjoint vectors, FP64 accumulation of dV and dR across regions)
-within 1e-5 at small K; at K = 80 the gradient sum
-dV(x) = sum_k alpha_k vt_{k+1}(x) v_k(x) cancels by ~3 orders of magnitude
-(|dV| ~ 4e-4 from O(1) terms), so FP32 vector rounding (2^-24 per step, over
-2K steps) leaves ~2.5e-4 max-norm relative error; that case is held to 1e-3.
-Finite differences always use the FP64 forward pass.
+forward context, and the precision the benchmark times) within 1e-10 max-norm
+relative of the oracle, at every region edge including 27.  The optional FP32
+adjoint (FP32 primal and adjoint vectors) within 1e-5 at small K; at K = 80..100
+the gradient sum dV(x) = sum_k alpha_k vt_{k+1}(x) v_k(x) cancels by three to
+four orders of magnitude, and FP32 rounding of any one of v_k, vt_k or the sum
+(2^-24 per step over 2K steps) leaves 1e-5..5e-4 max-norm relative error, so
+that variant is held to 1e-3 and is not the benchmarked one.  Finite
+differences always use the FP64 forward pass: a fourth-order central difference
+at delta = 1e-4 Ha agrees with the adjoint to ~3e-8 relative (truncation
+delta^4 and rounding eps |y| / delta both below that), held to 2e-7.
 """
 import numpy as np
 import pytest
@@ -91,9 +94,26 @@ def test_adjoint_accumulates_and_dV_only():
     assert dR_g is None and rel(dV_g, gV) < 1e-10
 
 
+def _fd_directional(prob, lmin, lmax, lf, g_rho, g_u, nodes, dvec, delta=1e-4):
+    """Fourth-order central difference of y = sum g_rho rho + g_u u along dvec,
+    from the FP64 forward pass on the node subset."""
+    from paper_2011_13517_amd import sq
+    ys = {}
+    for s in (2, 1, -1, -2):
+        ctx = sq.Context(prob, precision=0, nodes=nodes)
+        V = torch.tensor(prob.V + s * delta * dvec, dtype=torch.float64, device="cuda")
+        ctx.density(V, lmin, lmax)
+        lam = torch.tensor([lf], dtype=torch.float64, device="cuda")
+        _, rho, u, _ = ctx.fermi_level(max_iter=0, lambda_f=lam)
+        ys[s] = float((g_rho * rho.cpu().numpy()).sum() + (g_u * u.cpu().numpy()).sum())
+        ctx.close()
+    return (-ys[2] + 8 * ys[1] - 8 * ys[-1] + ys[-2]) / (12 * delta)
+
+
 def test_adjoint_config4_nodes_vs_oracle_and_fd():
-    """Config 4 geometry (48^3, 21^3 regions, K = 80, 63 atoms) on a node subset:
-    FP64 GPU vs oracle, FP32 GPU vs oracle, and a central difference of the FP64
+    """Config 4 geometry (48^3, 21^3 regions, K = 80, 63 atoms, one vacancy) on a
+    node subset: FP64 adjoint (FP64 and FP32 forward contexts) vs oracle at 1e-10,
+    the optional FP32 adjoint at its bound, and a central difference of the FP64
     forward pass along a random potential direction (delta = 1e-4 Ha)."""
     print("[case] adjoint config4 subset", flush=True)
     prob = synth.config(4)
@@ -111,37 +131,48 @@ def test_adjoint_config4_nodes_vs_oracle_and_fd():
     assert rel(dVm, gV) < 1e-10 and rel(dRm, dR) < 1e-10
     print(f"FP32 adjoint at K=80: dV rel {rel(dV32, gV):.2e}, dR rel {rel(dR32, dR):.2e}")
     assert rel(dV32, gV) < 1e-3 and rel(dR32, dR) < 1e-3
-    # directional derivative of y = sum g_rho rho + g_u u along d, by the fourth-order
-    # central difference of the FP64 forward pass (a second-order difference at
-    # delta = 1e-4 Ha is limited by its delta^2 k^6 truncation term at K = 80)
-    from paper_2011_13517_amd import sq
     dvec = np.zeros(prob.V.size)
     pts = rng.choice(np.flatnonzero(gV != 0), 512, replace=False)
     dvec[pts] = rng.uniform(-1, 1, 512)
-    eps = 1e-5
-    ys = {}
-    for s in (2, 1, -1, -2):
-        ctx = sq.Context(prob, precision=0, nodes=nodes)
-        V = torch.tensor(prob.V + s * eps * dvec, dtype=torch.float64, device="cuda")
-        ctx.density(V, lmin, lmax)
-        lam = torch.tensor([lf], dtype=torch.float64, device="cuda")
-        _, rho, u, _ = ctx.fermi_level(max_iter=0, lambda_f=lam)
-        ys[s] = float((g_rho * rho.cpu().numpy()).sum() + (g_u * u.cpu().numpy()).sum())
-        ctx.close()
-    fd = (-ys[2] + 8 * ys[1] - 8 * ys[-1] + ys[-2]) / (12 * eps)
+    fd = _fd_directional(prob, lmin, lmax, lf, g_rho, g_u, nodes, dvec)
     ad = float(dV64 @ dvec)
-    scale = float(np.abs(dV64 * dvec).sum())
-    print(f"directional derivative: fd {fd:.10e} adjoint {ad:.10e} (scale {scale:.3e})")
-    assert abs(fd - ad) < 1e-6 * scale, (fd, ad, scale)
+    print(f"directional derivative: fd {fd:.12e} adjoint {ad:.12e}")
+    assert abs(fd - ad) < 2e-7 * abs(ad), (fd, ad)
+
+
+def test_adjoint_config2_bench_launch():
+    """The benchmarked configuration (64^3, 27^3 regions, 12th-order FD, K = 100,
+    96 atoms) with the adjoint in the precision the benchmark times (FP64, the
+    edge-27 kernel) behind the FP32 forward context: sampled nodes against the
+    FP64 oracle at 1e-10 for dV and dR, and a central difference of the FP64
+    forward pass along a random potential direction."""
+    print("[case] adjoint config2 sample FP64 edge 27", flush=True)
+    prob = synth.config(2)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    lf = 0.5 * (lmin + lmax) - 0.4 * (lmax - lmin)
+    rng = np.random.default_rng(22)
+    nodes = np.sort(rng.choice(prob.n_nodes, 12, replace=False))
+    g_rho, g_u = _cotangents(nodes.size, 5)
+    gV, dR = oracle_adjoint(prob, lmin, lmax, lf, g_rho, g_u, nodes=nodes)
+    dV, dRg = gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 1, nodes=nodes, ckpt_every=1,
+                          adjoint_precision=0)
+    print(f"FP64 adjoint at K=100, 27^3: dV rel {rel(dV, gV):.2e}, dR rel {rel(dRg, dR):.2e}")
+    assert rel(dV, gV) < 1e-10 and rel(dRg, dR) < 1e-10
+    dvec = np.zeros(prob.V.size)
+    pts = rng.choice(np.flatnonzero(gV != 0), 512, replace=False)
+    dvec[pts] = rng.uniform(-1, 1, 512)
+    fd = _fd_directional(prob, lmin, lmax, lf, g_rho, g_u, nodes, dvec)
+    ad = float(dV @ dvec)
+    print(f"directional derivative: fd {fd:.12e} adjoint {ad:.12e}")
+    assert abs(fd - ad) < 2e-7 * abs(ad), (fd, ad)
 
 
 @pytest.mark.parametrize("ckpt", [0, 7])
-def test_adjoint_config2_bench_launch(ckpt):
-    """The benchmarked configuration (64^3, 27^3 regions, 12th-order FD, K = 100,
-    96 atoms): FP32 adjoint in the launch configuration the benchmark times
-    (store-all by default; rebuild with ckpt 7) on sampled nodes against the FP64
-    oracle, held to the FP32 gradient tolerance of 1e-3 (see module docstring)."""
-    print(f"[case] adjoint config2 sample ckpt={ckpt}", flush=True)
+def test_fp32_adjoint_config2(ckpt):
+    """The optional FP32 adjoint at edge 27 (store-all by default; rebuild with
+    ckpt 7) on sampled nodes against the FP64 oracle, at the FP32 gradient bound
+    of 1e-3 (see the module docstring)."""
+    print(f"[case] FP32 adjoint config2 sample ckpt={ckpt}", flush=True)
     prob = synth.config(2)
     lmin, lmax = O.lanczos_bounds(prob, steps=60)
     lf = 0.5 * (lmin + lmax) - 0.4 * (lmax - lmin)
@@ -153,3 +184,47 @@ def test_adjoint_config2_bench_launch(ckpt):
                              adjoint_precision=1)
     print(f"FP32 adjoint at K=100, 27^3: dV rel {rel(dV32, gV):.2e}, dR rel {rel(dR32, dR):.2e}")
     assert rel(dV32, gV) < 1e-3 and rel(dR32, dR) < 1e-3
+
+
+def test_adjoint_config5_embedded_nodes():
+    """Embedded 128^3 workload (V and projectors on the 154^3 padded grid, K = 120):
+    the FP64 edge-27 adjoint on sampled nodes, the corners of Omega (regions
+    reaching into the padding) among them, against the oracle at 1e-10."""
+    print("[case] adjoint config5 embedded sample", flush=True)
+    prob = synth.config(5)
+    lmin, lmax = O.gershgorin(prob)
+    n0, n1, n2 = prob.n
+    corners = [i + n0 * (j + n1 * k) for i in (0, n0 - 1) for j in (0, n1 - 1)
+               for k in (0, n2 - 1)]
+    rng = np.random.default_rng(57)
+    nodes = np.unique(np.concatenate([corners, rng.choice(prob.n_nodes, 8, replace=False)]))
+    lf = 0.5 * (lmin + lmax) - 0.45 * (lmax - lmin)
+    g_rho, g_u = _cotangents(nodes.size, 7)
+    gV, dR = oracle_adjoint(prob, lmin, lmax, lf, g_rho, g_u, nodes=nodes)
+    dV, dRg = gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 1, nodes=nodes, adjoint_precision=0)
+    print(f"config 5 FP64 adjoint: dV rel {rel(dV, gV):.2e}, dR rel {rel(dRg, dR):.2e}")
+    assert np.abs(dR).max() > 0
+    assert rel(dV, gV) < 1e-10 and rel(dRg, dR) < 1e-10
+
+
+@pytest.mark.parametrize("order", [11, 12])
+def test_fp64_adjoint_edge27_clipped_boxes(order):
+    """The FP64 edge-27 kernel on ragged Dirichlet-clipped boxes (edges 14..27 per
+    axis, some in the 27 bucket with dz < 27), odd and even K, dV + dR and dV
+    alone, against the oracle at 1e-10."""
+    print(f"[case] FP64 adjoint edge27 clipped K={order}", flush=True)
+    prob = synth.small_problem(81, n=(30, 28, 32), h=(0.5, 0.5, 0.5), bc=synth.BC_DIRICHLET,
+                               rcut=(13, 13, 13), n_atoms=6, rc=1.4, order=order, kT=0.2,
+                               fd_order=6)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    lf = 0.5 * (lmin + lmax) - 0.3 * (lmax - lmin)
+    n0, n1, n2 = prob.n
+    rng = np.random.default_rng(order)
+    picks = [0, n0 - 1 + n0 * (n1 - 1) * n2 // n2, (n0 // 2) + n0 * ((n1 // 2) + n1 * (n2 // 2))]
+    nodes = np.unique(np.concatenate([picks, rng.choice(prob.n_nodes, 9, replace=False)]))
+    g_rho, g_u = _cotangents(nodes.size, 11)
+    gV, dR = oracle_adjoint(prob, lmin, lmax, lf, g_rho, g_u, nodes=nodes)
+    dV, dRg = gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 1, nodes=nodes, adjoint_precision=0)
+    assert rel(dV, gV) < 1e-10 and rel(dRg, dR) < 1e-10
+    dV2, none = gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 0, nodes=nodes, with_dR=False)
+    assert none is None and rel(dV2, gV) < 1e-10
