@@ -331,6 +331,35 @@ sq_status sq_scf(sq_ctx *ctx, const double *b, const double *phi_bc, double Ne,
                  double lambda_min, double lambda_max, const sq_scf_params *params, double *V,
                  double *rho, double *lambda_f, sq_scf_info *info, void *stream);
 
+/* The Fermi-level solve of sq_fermi_level, without a context and without any
+ * allocation: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Given
+ * the moment sums M_k of a density pass (sq_density's moment_sum) and the
+ * scaling bounds that pass used, it bisects N_e(lambda_f) = 2 (c_0 M_0/2 +
+ * sum_k c_k M_k) = Ne_target exactly as sq_fermi_level does (same kernels, same
+ * rule, same Chebyshev-Gauss rule for the coefficients) and gives the same
+ * lambda_f and totals.  Its scratch (bracket, partial sums, the rule's sums) is
+ * one static array of 8.6 MB per GPU, kept until the process ends.
+ *   M            device [K+1] FP64 moment sums (read only).
+ *   K            Chebyshev degree, 1..512.
+ *   lambda_min,
+ *   lambda_max   the bounds the moments were scaled with (finite, max > min).
+ *   kT           smearing in Ha (> 0); kT / tau must leave the coefficient rule
+ *                at most 2^20 points (8 / (kT / tau) <= 2^20), else SQ_ERR_ARG.
+ *   Ne_target, tol_Ne, max_iter   as in sq_fermi_level (max_iter 0: *lambda_f
+ *                is an input and no bisection runs).
+ *   lambda_f     device scalar FP64, output (input when max_iter == 0).
+ *   coef         device [4][K+1] FP64 output {c', d', dc'/dlambda_f,
+ *                dd'/dlambda_f} (c'_0 = c_0/2), or NULL.
+ *   totals       device [8] FP64 output as in sq_fermi_level, or NULL.
+ * Every call on a GPU uses that GPU's one scratch array: calls that overlap on
+ * one GPU (two streams, two threads) race and must be serialised by the
+ * caller.  Host-detectable argument errors return at the call; the device
+ * status goes to totals[7]. */
+sq_status sq_fermi_level_noalloc(const double *M, int32_t K, double lambda_min, double lambda_max,
+                                 double kT, double Ne_target, double tol_Ne, int32_t max_iter,
+                                 double *lambda_f, double *coef, double *totals, void *stream);
+
 /* Synchronises the context's last stream and returns the device-side status
  * word (SQ_OK, SQ_ERR_NOT_CONVERGED, SQ_ERR_ARG on region atom-list overflow). */
 sq_status sq_device_status(sq_ctx *ctx);

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "SQ_OK", -1: "SQ_ERR_ARG", -2: "SQ_ERR_HIP", -3: "SQ_ERR_OOM"
 # every entry point declared in include/sq.h
 EXPORTS = ("sq_setup", "sq_destroy", "sq_last_error", "sq_get_info", "sq_density",
            "sq_fermi_level", "sq_entropy", "sq_gauss_density", "sq_gauss_fermi_level", "sq_nonlocal_force", "sq_scf",
-           "sq_density_backward", "sq_device_status")
+           "sq_density_backward", "sq_device_status", "sq_fermi_level_noalloc")
 
 
 class sq_params(C.Structure):
@@ -104,6 +104,8 @@ def lib():
         L.sq_density_backward.restype = C.c_int
         L.sq_device_status.argtypes = [VP]
         L.sq_device_status.restype = C.c_int
+        L.sq_fermi_level_noalloc.argtypes = [VP, I32, D, D, D, D, D, I32, VP, VP, VP, VP]
+        L.sq_fermi_level_noalloc.restype = C.c_int
         _lib = L
     return _lib
 

@@ -73,6 +73,14 @@ void fd_first_weights(int r, double *w) {
 
 }  // namespace
 
+// error reporting for entry points defined in other sources of the library
+namespace sqk {
+sq_status set_error(sq_status st, const char *msg) {
+    g_err = msg;
+    return st;
+}
+}  // namespace sqk
+
 // A launch group: a contiguous range of the sorted work list run by one
 // persistent kernel instantiated for edge bucket E.
 struct Group {

@@ -135,6 +135,9 @@ int64_t adjoint64_slot_elems(int K, int E);
 hipError_t launch_adjoint64(int E, int R, bool grad, const void *args, int grid, hipStream_t s);
 int adjoint64_blocks_per_cu(int E, int R, bool grad);
 
+// Sets the thread-local message returned by sq_last_error and returns st.
+sq_status set_error(sq_status st, const char *msg);
+
 // Region-edge buckets with a compiled kernel (the largest edge of every box
 // must not exceed the bucket).
 constexpr int EDGE_BUCKETS[] = {9, 13, 17, 21, 27, 32};
