@@ -4,20 +4,14 @@
 namespace sqk {
 
 namespace {
-template <int R>
-hipError_t a64_by_grad(bool grad, const void *args, int grid, hipStream_t s, int *occ) {
-    return grad ? a64_launch_one<R, true>(args, grid, s, occ)
-                : a64_launch_one<R, false>(args, grid, s, occ);
-}
-
-hipError_t a64_dispatch(int R, bool grad, const void *args, int grid, hipStream_t s, int *occ) {
+hipError_t a64_dispatch(int R, const void *args, int grid, hipStream_t s, int *occ) {
     switch (R) {
-        case 1: return a64_by_grad<1>(grad, args, grid, s, occ);
-        case 2: return a64_by_grad<2>(grad, args, grid, s, occ);
-        case 3: return a64_by_grad<3>(grad, args, grid, s, occ);
-        case 4: return a64_by_grad<4>(grad, args, grid, s, occ);
-        case 5: return a64_by_grad<5>(grad, args, grid, s, occ);
-        case 6: return a64_by_grad<6>(grad, args, grid, s, occ);
+        case 1: return a64_launch_one<1>(args, grid, s, occ);
+        case 2: return a64_launch_one<2>(args, grid, s, occ);
+        case 3: return a64_launch_one<3>(args, grid, s, occ);
+        case 4: return a64_launch_one<4>(args, grid, s, occ);
+        case 5: return a64_launch_one<5>(args, grid, s, occ);
+        case 6: return a64_launch_one<6>(args, grid, s, occ);
         default: return hipErrorInvalidValue;
     }
 }
@@ -29,12 +23,14 @@ int64_t adjoint64_slot_elems(int K, int E) { return a64_slot_elems(K, E); }
 
 hipError_t launch_adjoint64(int E, int R, bool grad, const void *args, int grid, hipStream_t s) {
     if (E != A64_EDGE) return hipErrorInvalidValue;
-    return a64_dispatch(R, grad, args, grid, s, nullptr);
+    (void)grad;   // dR is formed in the final pass when requested
+    return a64_dispatch(R, args, grid, s, nullptr);
 }
 
 int adjoint64_blocks_per_cu(int E, int R, bool grad) {
     int occ = 1;
-    if (E == A64_EDGE) (void)a64_dispatch(R, grad, nullptr, 0, nullptr, &occ);
+    (void)grad;
+    if (E == A64_EDGE) (void)a64_dispatch(R, nullptr, 0, nullptr, &occ);
     return occ;
 }
 

@@ -280,9 +280,10 @@ __device__ __forceinline__ void diag_part(const RegionArgs<T> &a, const StepCtx<
         asm volatile("" : "+s"(salt));
         const uint32_t cl = (uint32_t)col;
         const int zmax = c.dz - 1 + salt;
-        // all loads first, then the FMAs: one memory wait per step (left
-        // alone, the allocator issues load, wait, FMA per z)
-        constexpr int CH = E;
+        // all loads of a batch first, then its FMAs: one memory wait per batch
+        // (left alone, the allocator issues load, wait, FMA per z); FP64 pencils
+        // go in batches of 9 so the loads do not need 2E registers at once
+        constexpr int CH = sizeof(T) == 8 ? 9 : E;
 #pragma unroll
         for (int z0 = 0; z0 < E; z0 += CH) {
             T dv[CH];
@@ -441,10 +442,15 @@ __device__ __forceinline__ void merge_equal_slots(T (&v)[NV], int &slot) {
 
 // The support rows of a column piece are read in batches of NB (loads of the
 // batch first, then its FMAs), so one L2 round trip serves NB rows.
+#ifndef SQ_NB64
+#define SQ_NB64 2
+#endif
+constexpr int NB64 = SQ_NB64;   // FP64 batch
 template <typename T, bool GRAD>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
                                          const T *pencil) {
-    constexpr int NB = GRAD ? 2 : 4;
+    // FP64 batches stay small: the two FP64 pencils already hold 4E VGPRs
+    constexpr int NB = sizeof(T) == 8 ? (GRAD ? 1 : NB64) : (GRAD ? 2 : 4);
     // every lane runs the wave's largest column count (the DPP merge needs its
     // partner lanes active); lanes past their own count contribute nothing
     int ncw = nl.ncol;
@@ -517,7 +523,7 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
 template <typename T>
 __device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T> &nl, T *pencil,
                                            T half) {
-    constexpr int NB = 4;
+    constexpr int NB = sizeof(T) == 8 ? NB64 : 4;
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         const T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
