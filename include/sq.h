@@ -85,7 +85,9 @@ typedef struct {
                          /* (9, 13, 17, 21, 27, 32): 0 = sq_setup times one launch   */
                          /* at the largest bucket against one launch per bucket on   */
                          /* a sample of the regions and keeps the faster (cached per */
-                         /* geometry in the process); 1 = one launch per bucket      */
+                         /* geometry in the process); 1 = one launch per bucket;     */
+                         /* 2 = one launch of one workgroup per region (the plain,   */
+                         /* unbatched path, kept as the baseline of the batching)    */
 } sq_params;
 
 /* Nonlocal Kleinman-Bylander projectors (Section 2.1, the nonlocal operator

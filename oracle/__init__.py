@@ -72,6 +72,7 @@ def lib():
         L.orc_splitmix_uniform.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix_uniform.restype = D
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
         _lib = L
@@ -115,6 +116,11 @@ class _Bound:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's node loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def fd_weights(r: int) -> np.ndarray:

@@ -61,6 +61,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* threads of the node loops from here on (timing on one core or all) */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* FD weights: central second derivative, radius r (2r-th order accurate).     */
 /* w_p = 2 (-1)^{p+1} (r!)^2 / (p^2 (r-p)! (r+p)!),  w_0 = -2 sum_{p>=1} w_p.   */

@@ -90,17 +90,29 @@ struct Group {
     int grid_fwd = 1, grid_adj = 1;
     int grid_gauss = 0;   // set on the first Gauss sweep
 };
-enum { PLAN_MERGED = 0, PLAN_SPLIT = 1 };
+enum { PLAN_MERGED = 0, PLAN_SPLIT = 1, PLAN_PER_REGION = 2 };
 
 static int item_bucket(const Item &it) {
     return edge_bucket(std::max(it.dim[0], std::max(it.dim[1], it.dim[2])));
 }
 
-// groups of a sorted work list: one group at the largest bucket (merged), or
-// one group per edge bucket (split)
+// groups of a sorted work list: one group at the largest bucket (merged), one
+// group per edge bucket (split), or one launch of one workgroup per region (the
+// plain, unbatched path)
 static std::vector<Group> make_groups(const std::vector<Item> &items, int plan) {
     std::vector<Group> g;
     const int n = (int)items.size();
+    if (plan == PLAN_PER_REGION) {
+        for (int i = 0; i < n; ++i) {
+            Group gr;
+            gr.begin = i;
+            gr.count = 1;
+            gr.E = item_bucket(items[i]);
+            gr.maskz = items[i].dim[2] != gr.E;
+            g.push_back(gr);
+        }
+        return g;
+    }
     for (int i = 0; i < n;) {
         Group gr;
         gr.begin = i;
@@ -249,7 +261,7 @@ sq_status validate(const sq_params *p) {
     if (p->ckpt_every < 0) return fail(SQ_ERR_ARG, "ckpt_every must be >= 0");
     if (p->adjoint_precision != SQ_FP64 && p->adjoint_precision != SQ_FP32_ACC64)
         return fail(SQ_ERR_ARG, "adjoint_precision %d unknown", p->adjoint_precision);
-    if (p->tune != 0 && p->tune != 1) return fail(SQ_ERR_ARG, "tune %d unknown", p->tune);
+    if (p->tune < 0 || p->tune > 2) return fail(SQ_ERR_ARG, "tune %d unknown", p->tune);
     return SQ_OK;
 }
 
@@ -709,7 +721,8 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
         if ((st = c.upload(&(ptr), (src), (n))) != SQ_OK) return bail(st);  \
     } while (0)
     UPLOAD(c.d_items, items.data(), items.size());
-    ALLOC(c.d_counter, 64);
+    // one work counter per launch group (one per region for the plain plan)
+    ALLOC(c.d_counter, (size_t)std::max<int64_t>(64, c.p.tune == 2 ? n_nodes : 0));
     ALLOC(c.d_status, 4);
     ALLOC(c.d_scal, 1);
     if (c.prec == SQ_FP64 || c.aprec == SQ_FP64) ALLOC(c.d_D64, c.nv);
@@ -808,11 +821,17 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     grids(merged);
     grids(split);
     c.plan = split.size() > 1 ? PLAN_SPLIT : PLAN_MERGED;
-    if (split.size() > 1 && c.p.tune == 0) {
-        const sq_status ts = tune_plan(c, items, ncu);
-        if (ts != SQ_OK) return bail(ts);
+    if (c.p.tune == 2) {
+        c.plan = PLAN_PER_REGION;
+        c.groups = make_groups(items, PLAN_PER_REGION);
+        grids(c.groups);
+    } else {
+        if (split.size() > 1 && c.p.tune == 0) {
+            const sq_status ts = tune_plan(c, items, ncu);
+            if (ts != SQ_OK) return bail(ts);
+        }
+        c.groups = c.plan == PLAN_SPLIT ? split : merged;
     }
-    c.groups = c.plan == PLAN_SPLIT ? split : merged;
 
     // nonlocal force work list: nodes where some chi_Jlm is nonzero, one
     // launch per edge bucket

@@ -54,7 +54,7 @@ def _params(**kw):
 @pytest.mark.parametrize("kw", [dict(fd_order=3), dict(fd_order=14), dict(order=0),
                                 dict(kT=0.0), dict(bc=7), dict(precision=5), dict(h=[0.5, 0, 0.5]),
                                 dict(n=[8, 0, 8]), dict(rcut=[-1, 2, 2]), dict(ckpt_every=-1),
-                                dict(adjoint_precision=3), dict(tune=2), dict(tune=-1)])
+                                dict(adjoint_precision=3), dict(tune=3), dict(tune=-1)])
 def test_invalid_params_rejected(lib, kw):
     ctx = C.c_void_p()
     st = lib.sq_setup(C.byref(_params(**kw)), None, None, None, 512, C.byref(ctx))

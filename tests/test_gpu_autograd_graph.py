@@ -188,3 +188,61 @@ def test_graph_replay_gauss_and_force():
             assert (a - b).abs().max().item() <= tol * scale, (rep, i)
         assert abs(got[6][0].item() - Ne) < 1e-8
     ctx.close()
+
+
+def test_graph_replay_config3_split_plan():
+    """Config 3 (4096 uneven Dirichlet-clipped regions, K = 100, FP32) with one
+    persistent launch per edge bucket (several work counters and launches):
+    sq_density + sq_fermi_level (fixed lambda_f) captured once and replayed with
+    new potentials; every replay against an eager run on the same input, and the
+    replay of the unperturbed potential against the oracle on sampled nodes."""
+    from paper_2011_13517_amd import sq
+    print("[case] graph replay config3 split plan", flush=True)
+    prob = synth.config(3)
+    lmin, lmax = O.lanczos_bounds(prob, steps=60)
+    ctx = sq.Context(prob, precision=1, tune=1)
+    assert ctx.info.n_launches > 1
+    dev = torch.device("cuda")
+    n, K = ctx.n_nodes, ctx.K
+    V0 = torch.tensor(prob.V, dtype=torch.float64, device=dev)
+    V = V0.clone()
+    mu = torch.empty((n, K + 1), dtype=torch.float64, device=dev)
+    M = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    lam = torch.tensor([prob.lambda_f], dtype=torch.float64, device=dev)
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    tot = torch.empty(8, dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.density(V, lmin, lmax, moments=mu, moment_sum=M)
+        ctx.fermi_level(max_iter=0, lambda_f=lam, rho=rho, u=u, totals=tot)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    rng = np.random.default_rng(7)
+    for rep in range(3):
+        pert = 0.0 if rep == 0 else 0.05
+        V.copy_(V0 + torch.tensor(rng.uniform(-pert, pert, size=prob.V.shape), device=dev))
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [t.clone() for t in (mu, rho, u)]
+        step()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        for a, b in zip(got, (mu, rho, u)):
+            # FP32 projector sums use LDS atomics (order may vary); a stale input
+            # would differ by O(0.05)
+            assert (a - b).abs().max().item() <= 2e-5 * max(b.abs().max().item(), 1.0)
+        if rep == 0:
+            pick = np.sort(rng.choice(n, 12, replace=False))
+            mu_ref = O.moments(prob, lmin, lmax, nodes=prob.nodes[pick],
+                               node_m=prob.node_rcut[pick])
+            assert np.abs(got[0].cpu().numpy()[pick] - mu_ref).max() < K * 2.0 ** -24 * 8
+    ctx.close()

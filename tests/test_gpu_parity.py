@@ -151,11 +151,11 @@ def test_config2_sampled(precision):
     assert abs(g["tot"][0] - prob.Ne) < 1e-8 * prob.Ne
 
 
-@pytest.mark.parametrize("precision,tune", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("precision,tune", [(0, 0), (1, 0), (1, 1), (0, 2)])
 def test_config3_uneven_clipped(precision, tune):
     """4096 uneven Dirichlet-clipped regions (edges 11..27 before clipping):
-    the launch plan the tuner picks (tune 0), and one persistent launch per
-    edge bucket (tune 1)."""
+    the launch plan the tuner picks (tune 0), one persistent launch per edge
+    bucket (tune 1), and one launch per region (tune 2, the plain path)."""
     print(f"[case] config3 precision={precision} tune={tune}", flush=True)
     prob = synth.config(3)
     lmin, lmax = O.lanczos_bounds(prob, steps=60)
@@ -164,6 +164,8 @@ def test_config3_uneven_clipped(precision, tune):
     print(f"persistent launches per pass: {info[0].n_launches}")
     if tune == 1:
         assert info[0].n_launches > 1
+    elif tune == 2:
+        assert info[0].n_launches == prob.n_nodes
     else:
         assert info[0].n_launches >= 1
     nodes, widths = prob.nodes, prob.node_rcut
