@@ -23,7 +23,12 @@
 //  * Forward sweep: v_0 .. v_{K-1} go to the slot, and the projections
 //    p_k = chi . v_k that the recurrence forms anyway.  Reverse sweep: vt_{k+1}
 //    goes to the slot, and q_k = chi . vt_{k+1}.  No dchi projections are
-//    formed per step.
+//    formed per step.  Both live vectors of a sweep stay in registers (the one
+//    being advanced is updated in place; the other is published to the LDS box
+//    and read back after the step), so a step reads nothing back from the slot.
+//  * Slot rows and the diagonal are addressed as one block-uniform base plus a
+//    32-bit lane offset (one scalar pair per stream instead of one per plane);
+//    this bounds the V grid to A64_MAX_GRID points.
 //  * A final pass of each thread over its own pencil streams vt_{k+1}(z) and
 //    v_k(z) back from the slot and accumulates, in FP64 registers,
 //      dV(z) = (1/tau) sum_k alpha_k vt_{k+1}(z) v_k(z)
@@ -34,6 +39,8 @@
 //  * dV is added to the grid with FP64 atomics; dR is reduced per atom in LDS
 //    and added once per atom per region.
 #pragma once
+
+#include <utility>
 
 #include "sq_region.h"
 
@@ -50,10 +57,42 @@ __device__ __forceinline__ double uniform_f64(double x) {
 
 constexpr int A64_EDGE = 27;
 constexpr int A64_ATOMS = 48;      // atoms per box (the LDS left beside the FP64 box)
+constexpr int A64_DB = 9;          // planes of the diagonal per load batch
+#ifndef A64_NB
+#define A64_NB 2                   // support rows per load batch of the projector block
+#endif
+#ifndef A64_XY_SPLIT
+#define A64_XY_SPLIT 3             // x/y pipeline units per pencil (0: plain loop)
+#endif
+// V grids up to this many points keep every byte offset of the diagonal in 32 bits
+// (slot rows: K up to 512 keeps 2 K E^3 doubles below 2^32 bytes)
+constexpr int64_t A64_MAX_GRID = (int64_t)1 << 29;
 
-// slot of one workgroup (doubles): v_k rows and vt_{k+1} rows ([k][z][pencil],
-// E^3 each), projections p_k and q_k ([k][atom][NP] each), then the atom list
-// (Slot) and the column entries ([thread][MAXC] ColEntry) of the box
+// Slot rows and the diagonal are read and written with raw buffer
+// instructions: a resource in scalar registers, a 32-bit lane offset (one
+// VGPR per stream, whatever the plane) and a scalar plane offset.  The
+// resource's extent is the stream's byte size; in-range offsets are what the
+// kernel forms, and the hardware returns zero for (and drops) anything past it.
+typedef unsigned int a64_u2 __attribute__((ext_vector_type(2)));
+constexpr int A64_RSRC_WORD3 = 0x00020000;   // raw 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t a64_rsrc(const void *base, int64_t bytes) {
+    const uint32_t n = bytes >= (int64_t)0xffffffffLL ? 0xffffffffu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n,
+                                             A64_RSRC_WORD3);
+}
+// byte offsets: voff per lane, soff block-uniform
+__device__ __forceinline__ double a64_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const a64_u2 v =
+        __builtin_amdgcn_raw_buffer_load_b64(r, voff, __builtin_amdgcn_readfirstlane(soff), 0);
+    return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ void a64_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                       double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(a64_u2, x), r, voff,
+                                          __builtin_amdgcn_readfirstlane(soff), 0);
+}
+
 constexpr int64_t a64_proj_elems(int K) { return (int64_t)K * A64_ATOMS * NP; }
 constexpr int64_t a64_tables_elems(int E) {
     return ((int64_t)A64_ATOMS * sizeof(Slot) +
@@ -70,100 +109,214 @@ __device__ __forceinline__ void a64_store_proj(const ColNL<double> &nl, int nat,
     for (int i = threadIdx.x; i < nat * NP; i += BLOCK) row[i] = pa[i];
 }
 
-// One recurrence step with one pencil in registers:
-//   acc <- scale (2 Hs acc) - prev  (+ inj at plane inj_z of the owning thread),
-// scale = 1/2 on the first step.  On entry acc holds cur; cur is published to
-// the LDS box, and the register part (D cur - prev and the z neighbours) re-reads
-// cur from the thread's own LDS pencil in batches of ZB planes while acc is
-// overwritten batch by batch; prev (the vector two steps back) streams from its
-// slot row (PREV false: zero; a compile-time choice, so the batch of loads has
-// no branches between them).  The result is written to out_row.  The
-// projections chi . cur are left in parity buffer nl.par ^ 1.
-template <int E, int R, int ZS, int BLOCK, bool PREV>
-__device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
-                                         const StepCtx<double, E, R> &c, int64_t col,
-                                         int64_t plane, int gz0, int n2, double (&acc)[E],
-                                         double *lds, ColNL<double> &nl, bool first,
-                                         const double *prev_row, double *out_row, int inj_z,
-                                         double inj) {
-    constexpr int EE = E * E;
-    constexpr int ZB = 9;
-    if (c.active) store_pencil<double, E, ZS>(c.mine, acc);
-    __syncthreads();
-    if (c.nat) col_dots<double, false>(a, nl, c.mine);
-    if (c.active) {
-        int salt = 0;
-        asm volatile("" : "+s"(salt));
-        const uint32_t cl = (uint32_t)col;
-        const int zmax = c.dz - 1 + salt;
-        const uint32_t t = threadIdx.x;
+// x/y neighbours: acc += sum over the 4R neighbouring pencils of their
+// weight times the pencil, read from the LDS box in units of 1/NS pencil
+// through a two-deep pipeline: the reads of the next unit are in flight while
+// the FMAs of the current one run (left to itself the compiler issues the
+// reads one at a time, each waiting for the previous).  Every unit is its own
+// compile-time instance, so both buffers stay in registers.  A neighbour
+// outside the box is the zero pencil npen.
+struct A64Lane {
+    int tid, px, py;
+};
+
+template <int E, int R, int ZS, int NS, int U>
+__device__ __forceinline__ void a64_xy_load(double (&q)[(E + NS - 1) / NS],
+                                            const StepCtx<double, E, R> &c, const A64Lane &l,
+                                            const double *lds) {
+    constexpr int HZ = (E + NS - 1) / NS;
+    constexpr int j = U / NS, p = j / 4 + 1, dir = j % 4, z0 = (U % NS) * HZ;
+    int n;
+    if constexpr (dir == 0) n = (l.px + p < c.dx) ? l.tid + p : c.npen;
+    else if constexpr (dir == 1) n = (l.px - p >= 0) ? l.tid - p : c.npen;
+    else if constexpr (dir == 2) n = (l.py + p < c.dy) ? l.tid + p * c.dx : c.npen;
+    else n = (l.py - p >= 0) ? l.tid - p * c.dx : c.npen;
+    // 8-byte reads (pencils start at odd multiples of 8 bytes when ZS is odd);
+    // the compiler pairs them into two-address LDS reads
+    const double *b = lds + n * ZS + z0;
 #pragma unroll
-        for (int z0 = 0; z0 < E; z0 += ZB) {
-            double cw[ZB + 2 * R], dv[ZB], pv[ZB];
+    for (int i = 0; i < HZ; ++i)
+        if (z0 + i < E) q[i] = b[i];
+}
+
+template <int E, int R, int ZS, int NS, int U>
+__device__ __forceinline__ void a64_xy_unit(double (&acc)[E], double (&qa)[(E + NS - 1) / NS],
+                                            double (&qb)[(E + NS - 1) / NS],
+                                            const StepCtx<double, E, R> &c, const A64Lane &l,
+                                            const double *lds) {
+    constexpr int HZ = (E + NS - 1) / NS;
+    constexpr int NU = 4 * R * NS;
+    if constexpr (U + 1 < NU) {
+        if constexpr ((U + 1) & 1) a64_xy_load<E, R, ZS, NS, U + 1>(qb, c, l, lds);
+        else a64_xy_load<E, R, ZS, NS, U + 1>(qa, c, l, lds);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int j = U / NS, p = j / 4 + 1, z0 = (U % NS) * HZ;
+    const double w = (j % 4 < 2) ? c.cx[p] : c.cy[p];
+    const double(&q)[HZ] = (U & 1) ? qb : qa;
 #pragma unroll
-            for (int i = 0; i < ZB + 2 * R; ++i) {
-                const int z = z0 - R + i;
-                cw[i] = (z >= 0 && z < E) ? c.mine[z] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < ZB; ++i) {
-                if (z0 + i < E) {
-                    int gz = gz0 + min(z0 + i, zmax);
-                    gz = gz >= n2 ? gz - n2 : gz;
-                    dv[i] = sgpr_ptr(a.D + plane * gz)[cl];
-                    pv[i] = PREV ? sgpr_ptr(prev_row + (int64_t)(z0 + i) * EE)[t] : 0.0;
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < ZB; ++i) {
-                if (z0 + i < E) {
-                    double r = dv[i] * cw[i + R] - pv[i];
-#pragma unroll
-                    for (int p = 1; p <= R; ++p) r = fma(c.cz[p], cw[i + R + p] + cw[i + R - p], r);
-                    acc[z0 + i] = r;
-                }
-            }
-        }
-        // x/y neighbours from the LDS box (offsets recomputed from an opaque zero
-        // so that none of the 4R stays live across the step loop)
-        int s2 = 0;
-        asm volatile("" : "+v"(s2));
-        const int tid = threadIdx.x + s2;
-        const int px = c.px + s2, py = c.py + s2;
+    for (int i = 0; i < HZ; ++i)
+        if (z0 + i < E) acc[z0 + i] = fma(w, q[i], acc[z0 + i]);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int E, int R, int ZS, int NS, int... U>
+__device__ __forceinline__ void a64_xy_run(double (&acc)[E], const StepCtx<double, E, R> &c,
+                                           const A64Lane &l, const double *lds,
+                                           std::integer_sequence<int, U...>) {
+    double qa[(E + NS - 1) / NS], qb[(E + NS - 1) / NS];
+    a64_xy_load<E, R, ZS, NS, 0>(qa, c, l, lds);
+    (a64_xy_unit<E, R, ZS, NS, U>(acc, qa, qb, c, l, lds), ...);
+}
+
+template <int E, int R, int ZS>
+__device__ __forceinline__ void a64_xy(double (&acc)[E], const StepCtx<double, E, R> &c,
+                                       const double *lds) {
+    constexpr int NS = A64_XY_SPLIT;
+    // lane offsets recomputed from an opaque zero so that none of the 4R
+    // neighbour addresses stays live across the step loop
+    int s2 = 0;
+    asm volatile("" : "+v"(s2));
+    const A64Lane l{(int)threadIdx.x + s2, c.px + s2, c.py + s2};
+    if constexpr (NS > 0) {
+        a64_xy_run<E, R, ZS, NS>(acc, c, l, lds, std::make_integer_sequence<int, 4 * R * NS>{});
+    } else {
 #pragma unroll
         for (int p = 1; p <= R; ++p) {
-            const int n0 = (px + p < c.dx) ? tid + p : c.npen;
+            const int n0 = (l.px + p < c.dx) ? l.tid + p : c.npen;
             axpy_pencil<double, E, ZS>(acc, c.cx[p], lds + n0 * ZS);
-            const int n1 = (px - p >= 0) ? tid - p : c.npen;
+            const int n1 = (l.px - p >= 0) ? l.tid - p : c.npen;
             axpy_pencil<double, E, ZS>(acc, c.cx[p], lds + n1 * ZS);
-            const int n2_ = (py + p < c.dy) ? tid + p * c.dx : c.npen;
-            axpy_pencil<double, E, ZS>(acc, c.cy[p], lds + n2_ * ZS);
-            const int n3 = (py - p >= 0) ? tid - p * c.dx : c.npen;
+            const int n2 = (l.py + p < c.dy) ? l.tid + p * c.dx : c.npen;
+            axpy_pencil<double, E, ZS>(acc, c.cy[p], lds + n2 * ZS);
+            const int n3 = (l.py - p >= 0) ? l.tid - p * c.dx : c.npen;
             axpy_pencil<double, E, ZS>(acc, c.cy[p], lds + n3 * ZS);
         }
     }
+}
+
+// One recurrence step with the two live vectors in registers:
+//   v_{k+1} = scale (2 Hs v_k - v_{k-1})  (+ inj at plane inj_z of the owning
+// thread), scale = 1/2 on the first step.  On entry cur = v_k and nw = v_{k-1};
+// on exit cur = v_{k+1} and nw = v_k.  The new vector is formed in place in nw
+// and moved to cur after the second barrier.  cur is published to the LDS box (its
+// registers are free after the z neighbours, which are taken from them before
+// the first barrier, and it is re-read from the thread's own pencil after the
+// second barrier).  The diagonal D of the pencil is loaded in batches of
+// A64_DB planes, the first before the x/y neighbours (whose LDS work hides it)
+// and each next one before the diagonal term of the current batch.  The
+// result goes to slot row out (element offset; svo is the lane's byte offset
+// in a row, dvo its byte offset in a plane of D); the projections chi . cur are
+// left in parity buffer nl.par ^ 1.
+template <int E, int R, int ZS, int BLOCK>
+__device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
+                                         const StepCtx<double, E, R> &c,
+                                         __amdgpu_buffer_rsrc_t Dr, uint32_t dvo,
+                                         uint32_t plane, int gz0, int n2, double (&cur)[E],
+                                         double (&nw)[E], double *lds, ColNL<double> &nl,
+                                         bool first, __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
+                                         uint32_t out, int inj_z, double inj) {
+    constexpr int EE = E * E;
+    constexpr int DB = A64_DB;
+    constexpr int NDB = (E + DB - 1) / DB;
+    if (c.active) {
+        store_pencil<double, E, ZS>(c.mine, cur);
+        // z neighbours from the registers of cur (its last use in the step):
+        // nw <- sum_p cz_p (cur[z + p] + cur[z - p]) - nw
+#pragma unroll
+        for (int z = 0; z < E; ++z) {
+            double r = -nw[z];
+#pragma unroll
+            for (int p = 1; p <= R; ++p) {
+                if (z + p < E && z - p >= 0)
+                    r = fma(c.cz[p], cur[z + p] + cur[z - p], r);
+                else if (z + p < E)
+                    r = fma(c.cz[p], cur[z + p], r);
+                else if (z - p >= 0)
+                    r = fma(c.cz[p], cur[z - p], r);
+            }
+            nw[z] = r;
+        }
+    }
     __syncthreads();
+    if (c.nat) col_dots<double, false, A64_NB>(a, nl, c.mine);
+    if (c.active) {
+        // an opaque zero keeps the plane offsets from being hoisted out of the
+        // step loop
+        int salt = 0;
+        asm volatile("" : "+s"(salt));
+        const int zmax = c.dz - 1 + salt;
+        double d[NDB][DB];
+        auto load_d = [&](int b) {
+#pragma unroll
+            for (int i = 0; i < DB; ++i) {
+                const int z = b * DB + i;
+                if (z < E) {
+                    int gz = gz0 + min(z, zmax);
+                    gz = gz >= n2 ? gz - n2 : gz;
+                    d[b][i] = a64_ld(Dr, dvo, plane * (uint32_t)gz * 8u);
+                }
+            }
+        };
+        load_d(0);
+        // phase order is kept as written: a diagonal batch hoisted into the
+        // x/y part only adds live registers there
+        __builtin_amdgcn_sched_barrier(0);
+        a64_xy<E, R, ZS>(nw, c, lds);
+        __builtin_amdgcn_sched_barrier(0);
+        // diagonal: D times the own pencil, read back from the LDS box
+        int s3 = 0;
+        asm volatile("" : "+v"(s3));
+        const double *mw = c.mine + s3;
+#pragma unroll
+        for (int b = 0; b < NDB; ++b) {
+            if (b + 1 < NDB) load_d(b + 1);
+#pragma unroll
+            for (int i = 0; i < DB; ++i) {
+                const int z = b * DB + i;
+                if (z < E) nw[z] = fma(d[b][i], mw[z], nw[z]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __syncthreads();
+    // roles for the next step: cur <- the new vector, nw <- v_k (own pencil)
+#pragma unroll
+    for (int z = 0; z < E; ++z) cur[z] = nw[z];
+    if (c.active) load_pencil<double, E, ZS>(c.mine, nw);
     if (first) {
 #pragma unroll
-        for (int z = 0; z < E; ++z) acc[z] *= 0.5;
+        for (int z = 0; z < E; ++z) cur[z] *= 0.5;
     }
+    // planes past a z-clipped box edge: recomputed per step from an opaque
+    // copy of dz (hoisted, the E plane masks would pin 2E scalar registers)
+    {
+        int salt = 0;
+        asm volatile("" : "+s"(salt));
+        const int dz = c.dz + salt;
+        if (dz < E) {
 #pragma unroll
-    for (int z = 0; z < E; ++z) acc[z] = (z < c.dz) ? acc[z] : 0.0;
+            for (int z = 0; z < E; ++z) cur[z] = (z < dz) ? cur[z] : 0.0;
+        }
+    }
     if (c.nat) {
-        if (c.active) store_pencil<double, E, ZS>(c.mine, acc);
-        if (nl.ncol) col_update<double>(a, nl, c.mine, first ? 0.5 : 1.0);
-        if (c.active) load_pencil<double, E, ZS>(c.mine, acc);
+        if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
+        if (nl.ncol) col_update<double, A64_NB>(a, nl, c.mine, first ? 0.5 : 1.0);
+        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
         col_zero_next<double, BLOCK, false>(nl, c.nat);
     }
     nl.par ^= 1;
+    // the node's own lane only; its plane compares are redone per step (an
+    // opaque copy of inj_z) instead of E masks held across the loop
     if (inj_z >= 0) {
+        int iz = inj_z;
+        asm volatile("" : "+v"(iz));
 #pragma unroll
-        for (int z = 0; z < E; ++z) acc[z] += (z == inj_z) ? inj : 0.0;
+        for (int z = 0; z < E; ++z) cur[z] += (z == iz) ? inj : 0.0;
     }
-    if (c.active && out_row) {
+    if (c.active) {
 #pragma unroll
-        for (int z = 0; z < E; ++z) sgpr_ptr(out_row + (int64_t)z * EE)[threadIdx.x] = acc[z];
+        for (int z = 0; z < E; ++z) a64_st(Sr, svo, (out + (uint32_t)(z * EE)) * 8u, cur[z]);
     }
 }
 
@@ -195,8 +348,12 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         c.cz[p] = uniform_f64(-a.w[p] * a.ih2[2] / tau);
     }
     T *slot = aa.ckpt + (int64_t)blockIdx.x * aa.ckpt_stride;
-    T *Vrow = slot;                          // v_k       at Vrow + k E^3
-    T *Trow = slot + (int64_t)K * E3;        // vt_{k+1}  at Trow + k E^3
+    // slot rows at element offsets: v_k at k E^3, vt_{k+1} at (K + k) E^3
+    const __amdgpu_buffer_rsrc_t Sr = a64_rsrc(slot, 2 * (int64_t)K * E3 * 8);
+    const __amdgpu_buffer_rsrc_t Dr =
+        a64_rsrc(a.D, (int64_t)a.N[0] * a.N[1] * a.N[2] * 8);
+    const uint32_t VO = 0, TO = (uint32_t)(K * E3);
+    const uint32_t svo = (uint32_t)tid * 8u;
     T *Prow = slot + 2 * (int64_t)K * E3;    // p_k = chi . v_k        [k][atom][NP]
     T *Qrow = Prow + a64_proj_elems(K);      // q_k = chi . vt_{k+1}   [k][atom][NP]
     Slot *slots = reinterpret_cast<Slot *>(Qrow + a64_proj_elems(K));
@@ -208,7 +365,9 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
             s_nat = 0;
         }
         __syncthreads();
-        const int itn = s_item;
+        // block-uniform: the item and everything derived from it stay in
+        // scalar registers
+        const int itn = __builtin_amdgcn_readfirstlane(s_item);
         if (itn >= a.n_items) break;
         const Item it = a.items[itn];
         c.dx = it.dim[0];
@@ -235,7 +394,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         c.py = py;
         c.npen = npen;
         __syncthreads();
-        c.nat = min(s_nat, AT);
+        c.nat = min(__builtin_amdgcn_readfirstlane(s_nat), AT);
         if (tid == 0 && s_nat > AT) atomicOr(a.status, 1);
         const double gr = aa.g_rho ? aa.g_rho[it.out] : 0.0;
         const double gu = aa.g_u ? aa.g_u[it.out] : 0.0;
@@ -264,57 +423,57 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         __syncthreads();
 
         // ---- forward sweep: v_0 .. v_{K-1} and p_k = chi . v_k to the slot ----
-        T acc[E];
+        // X = cur, Y = prev; each step leaves the next pair in place
+        const uint32_t dvo = (uint32_t)col * 8u, pl = (uint32_t)plane;
+        T X[E], Y[E];
 #pragma unroll
-        for (int z = 0; z < E; ++z) acc[z] = (is_ctr && z == cz0) ? 1.0 : 0.0;
+        for (int z = 0; z < E; ++z) {
+            X[z] = (is_ctr && z == cz0) ? 1.0 : 0.0;
+            Y[z] = 0.0;
+        }
         if (c.active)
-            for (int z = 0; z < E; ++z) sgpr_ptr(Vrow + (int64_t)z * EE)[tid] = acc[z];
+            for (int z = 0; z < E; ++z) a64_st(Sr, svo, (VO + (uint32_t)(z * EE)) * 8u, X[z]);
         for (int k = 0; k + 1 <= K - 1; ++k) {
-            if (k == 0)
-                a64_step<E, R, ZS, BLOCK, false>(a, c, col, plane, gz0, n2, acc, lds, nl, true,
-                                                 nullptr, Vrow + E3, -1, 0.0);
-            else
-                a64_step<E, R, ZS, BLOCK, true>(a, c, col, plane, gz0, n2, acc, lds, nl, false,
-                                                Vrow + (k - 1) * E3, Vrow + (k + 1) * E3, -1, 0.0);
+            a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, k == 0,
+                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0);
             a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)k * AT * NP);
         }
-        // acc = v_{K-1}: its projections without a step
-        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, acc, nl);
+        // X = v_{K-1}: its projections without a step
+        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, X, nl);
         a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)(K - 1) * AT * NP);
 
         // ---- reverse sweep: vt_{k+1} and q_k = chi . vt_{k+1} to the slot ----
+        // vt_k = a_k e_q + 2 Hs vt_{k+1} - vt_{k+2}  (vt_{K+1} = 0)
         const T aK = 2.0 * (gr * aa.coef_c[K] + gu * aa.coef_d[K]);
 #pragma unroll
-        for (int z = 0; z < E; ++z) acc[z] = (is_ctr && z == cz0) ? aK : 0.0;   // vt_K
+        for (int z = 0; z < E; ++z) {
+            X[z] = (is_ctr && z == cz0) ? aK : 0.0;   // vt_K
+            Y[z] = 0.0;
+        }
         if (c.active)
-            for (int z = 0; z < E; ++z) sgpr_ptr(Trow + (K - 1) * E3 + (int64_t)z * EE)[tid] = acc[z];
+            for (int z = 0; z < E; ++z)
+                a64_st(Sr, svo, (TO + (uint32_t)((K - 1) * E3 + z * EE)) * 8u, X[z]);
+        const int iz = is_ctr ? cz0 : -1;
         for (int k = K - 1; k >= 1; --k) {
-            // vt_k = a_k e_q + 2 Hs vt_{k+1} - vt_{k+2}   (vt_{K+1} = 0)
             const T ak = 2.0 * (gr * aa.coef_c[k] + gu * aa.coef_d[k]);
-            if (k == K - 1)
-                a64_step<E, R, ZS, BLOCK, false>(a, c, col, plane, gz0, n2, acc, lds, nl, false,
-                                                 nullptr, Trow + (k - 1) * E3, is_ctr ? cz0 : -1,
-                                                 ak);
-            else
-                a64_step<E, R, ZS, BLOCK, true>(a, c, col, plane, gz0, n2, acc, lds, nl, false,
-                                                Trow + (k + 1) * E3, Trow + (k - 1) * E3,
-                                                is_ctr ? cz0 : -1, ak);
+            a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, false,
+                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak);
             a64_store_proj<BLOCK>(nl, c.nat, Qrow + (int64_t)k * AT * NP);
         }
-        // acc = vt_1: its projections q_0 without a step
-        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, acc, nl);
+        // X = vt_1: its projections q_0 without a step
+        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, X, nl);
         a64_store_proj<BLOCK>(nl, c.nat, Qrow);
         __syncthreads();   // the slot's projection rows are read by other threads below
 
         // ---- dV: G(z) = sum_k alpha_k vt_{k+1}(z) v_k(z), own pencil, FP64 ----
         if (aa.dV && c.active) {
-            T G[E];
-#pragma unroll
-            for (int z = 0; z < E; ++z) G[z] = 0.0;
             constexpr int ZB = 9;   // planes per pass (loads in flight vs registers)
-            const uint32_t t = (uint32_t)tid;
+            const double itau = 1.0 / tau;
 #pragma unroll
             for (int z0 = 0; z0 < E; z0 += ZB) {
+                T G[ZB];
+#pragma unroll
+                for (int i = 0; i < ZB; ++i) G[i] = 0.0;
                 // two steps per iteration: 4 ZB loads in flight
                 for (int k = 0; k < K; k += 2) {
                     const bool two = k + 1 < K;
@@ -324,28 +483,31 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
 #pragma unroll
                     for (int i = 0; i < ZB; ++i) {
                         if (z0 + i < E) {
-                            tv[0][i] = sgpr_ptr(Trow + k * E3 + (int64_t)(z0 + i) * EE)[t];
-                            vv[0][i] = sgpr_ptr(Vrow + k * E3 + (int64_t)(z0 + i) * EE)[t];
-                            tv[1][i] = sgpr_ptr(Trow + k1 * E3 + (int64_t)(z0 + i) * EE)[t];
-                            vv[1][i] = sgpr_ptr(Vrow + k1 * E3 + (int64_t)(z0 + i) * EE)[t];
+                            const uint32_t o0 = (uint32_t)(k * E3 + (z0 + i) * EE);
+                            const uint32_t o1 = (uint32_t)(k1 * E3 + (z0 + i) * EE);
+                            tv[0][i] = a64_ld(Sr, svo, (TO + o0) * 8u);
+                            vv[0][i] = a64_ld(Sr, svo, (VO + o0) * 8u);
+                            tv[1][i] = a64_ld(Sr, svo, (TO + o1) * 8u);
+                            vv[1][i] = a64_ld(Sr, svo, (VO + o1) * 8u);
                         }
                     }
 #pragma unroll
                     for (int i = 0; i < ZB; ++i) {
                         if (z0 + i < E) {
-                            G[z0 + i] = fma(a0 * tv[0][i], vv[0][i], G[z0 + i]);
-                            G[z0 + i] = fma(a1 * tv[1][i], vv[1][i], G[z0 + i]);
+                            G[i] = fma(a0 * tv[0][i], vv[0][i], G[i]);
+                            G[i] = fma(a1 * tv[1][i], vv[1][i], G[i]);
                         }
                     }
                 }
-            }
-            const double itau = 1.0 / tau;
+                // this batch of planes is complete: to the grid
 #pragma unroll
-            for (int z = 0; z < E; ++z) {
-                if (z < c.dz) {
-                    int gz = gz0 + z;
-                    gz = gz >= n2 ? gz - n2 : gz;
-                    unsafeAtomicAdd(aa.dV + col + plane * gz, G[z] * itau);
+                for (int i = 0; i < ZB; ++i) {
+                    const int z = z0 + i;
+                    if (z < E && z < c.dz) {
+                        int gz = gz0 + z;
+                        gz = gz >= n2 ? gz - n2 : gz;
+                        unsafeAtomicAdd(aa.dV + col + plane * gz, G[i] * itau);
+                    }
                 }
             }
         }
@@ -383,10 +545,12 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
                             // so the row address is a per-lane one
 #pragma unroll
                             for (int r = 0; r < RB; ++r) {
-                                const int64_t o =
-                                    kk * E3 + (int64_t)(e.zlo + min(i0 + r, e.n - 1)) * EE + tid;
-                                tv[h][r] = Trow[o];
-                                vv[h][r] = Vrow[o];
+                                // z differs between lanes: the plane goes into
+                                // the lane offset, the step into the scalar one
+                                const uint32_t vo =
+                                    (uint32_t)((e.zlo + min(i0 + r, e.n - 1)) * EE + tid) * 8u;
+                                tv[h][r] = a64_ld(Sr, vo, (TO + (uint32_t)(kk * E3)) * 8u);
+                                vv[h][r] = a64_ld(Sr, vo, (VO + (uint32_t)(kk * E3)) * 8u);
                             }
                         }
 #pragma unroll

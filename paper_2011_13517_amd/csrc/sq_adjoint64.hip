@@ -21,6 +21,8 @@ bool adjoint64_edge(int prec, int E) { return prec == SQ_FP64 && E == A64_EDGE; 
 
 int64_t adjoint64_slot_elems(int K, int E) { return a64_slot_elems(K, E); }
 
+int64_t adjoint64_max_grid() { return A64_MAX_GRID; }
+
 hipError_t launch_adjoint64(int E, int R, bool grad, const void *args, int grid, hipStream_t s) {
     if (E != A64_EDGE) return hipErrorInvalidValue;
     (void)grad;   // dR is formed in the final pass when requested

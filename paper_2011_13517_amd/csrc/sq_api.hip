@@ -185,6 +185,7 @@ struct sq_ctx {
     FermiWork fw{};
     // adjoint
     bool adj_ok = false;
+    bool adj_grid_ok = true;   // V grid within the FP64 edge-27 kernel's offset range
     bool storeall = false;
     int n_ckpt = 1;
     int64_t ckpt_stride = 0;
@@ -865,6 +866,11 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     // adjoint: one vector slot per resident workgroup, shared by the groups
     c.adj_ok = true;
     for (const Group &g : c.groups) c.adj_ok = c.adj_ok && g.E <= adjoint_max_edge(c.aprec);
+    for (const Group &g : c.groups)
+        if (adjoint64_edge(c.aprec, g.E) &&
+            (int64_t)c.N[0] * c.N[1] * c.N[2] > adjoint64_max_grid())
+            c.adj_grid_ok = false;
+    c.adj_ok = c.adj_ok && c.adj_grid_ok;
     if (c.adj_ok) {
         const bool grad = c.n_atoms > 0 && c.have_dchi;
         const int64_t esz = c.aprec == SQ_FP64 ? 8 : 4;
@@ -1001,6 +1007,10 @@ sq_status sq_density_backward(sq_ctx *ctx, const double *g_rho, const double *g_
     sq_ctx &c = *ctx;
     if (!c.have_fermi)
         return fail(SQ_ERR_STATE, "sq_density_backward needs sq_density and sq_fermi_level first");
+    if (!c.adj_grid_ok)
+        return fail(SQ_ERR_ARG, "the FP64 adjoint of edge-%d regions supports V grids of up to "
+                    "%lld points (this context: %lld)", c.E, (long long)adjoint64_max_grid(),
+                    (long long)c.N[0] * c.N[1] * c.N[2]);
     if (!c.adj_ok)
         return fail(SQ_ERR_ARG, "the %s adjoint supports region edges up to %d (this context: %d)",
                     c.aprec == SQ_FP64 ? "FP64" : "FP32", adjoint_max_edge(c.aprec), c.E);

@@ -127,10 +127,12 @@ hipError_t launch_adjoint(int prec, int E, int R, bool storeall, bool grad, cons
                           int grid, hipStream_t s);
 int adjoint_blocks_per_cu(int prec, int E, int R, bool storeall, bool grad);
 int adjoint_max_edge(int prec);
-// FP64 adjoint for the largest bucket (edge 27: the FP64 box fills the LDS, so
-// the projector block runs one wave per atom); its slot per workgroup holds
-// v_k, vt_{k+1}, the forward projections and the atom list (doubles).
+// FP64 adjoint for the largest bucket (edge 27: the FP64 box fills the LDS);
+// its slot per workgroup holds v_k, vt_{k+1}, the forward and reverse
+// projections, the atom list and the column entries (doubles).  Its 32-bit
+// stream offsets bound the V grid to adjoint64_max_grid() points.
 bool adjoint64_edge(int prec, int E);
+int64_t adjoint64_max_grid();
 int64_t adjoint64_slot_elems(int K, int E);
 hipError_t launch_adjoint64(int E, int R, bool grad, const void *args, int grid, hipStream_t s);
 int adjoint64_blocks_per_cu(int E, int R, bool grad);

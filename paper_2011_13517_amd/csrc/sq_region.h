@@ -446,11 +446,12 @@ __device__ __forceinline__ void merge_equal_slots(T (&v)[NV], int &slot) {
 #define SQ_NB64 2
 #endif
 constexpr int NB64 = SQ_NB64;   // FP64 batch
-template <typename T, bool GRAD>
+template <typename T, bool GRAD, int NBX = 0>
 __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> &nl,
                                          const T *pencil) {
     // FP64 batches stay small: the two FP64 pencils already hold 4E VGPRs
-    constexpr int NB = sizeof(T) == 8 ? (GRAD ? 1 : NB64) : (GRAD ? 2 : 4);
+    // (NBX > 0: a caller with registers to spare sets the batch)
+    constexpr int NB = NBX > 0 ? NBX : sizeof(T) == 8 ? (GRAD ? 1 : NB64) : (GRAD ? 2 : 4);
     // every lane runs the wave's largest column count (the DPP merge needs its
     // partner lanes active); lanes past their own count contribute nothing
     int ncw = nl.ncol;
@@ -520,10 +521,10 @@ __device__ __forceinline__ void col_dots(const RegionArgs<T> &a, const ColNL<T> 
 }
 
 // rank-4 update of this thread's own pencil in LDS (no other thread writes it)
-template <typename T>
+template <typename T, int NBX = 0>
 __device__ __forceinline__ void col_update(const RegionArgs<T> &a, const ColNL<T> &nl, T *pencil,
                                            T half) {
-    constexpr int NB = sizeof(T) == 8 ? NB64 : 4;
+    constexpr int NB = NBX > 0 ? NBX : sizeof(T) == 8 ? NB64 : 4;
     for (int c = 0; c < nl.ncol; ++c) {
         const ColEntry e = nl.cols[c];
         const T *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
