@@ -195,6 +195,89 @@ __device__ __forceinline__ void a64_xy(double (&acc)[E], const StepCtx<double, E
     }
 }
 
+// Projector block of the FP64 kernel (column path, as col_dots / col_update
+// in sq_region.h) with the per-region constants taken out of the step: the
+// wave's largest column count ncw is formed once per region, and the (at most
+// MAXC) column entries of a lane are loaded in one batch at the start of each
+// routine instead of one dependent round trip per entry.
+__device__ __forceinline__ int a64_wave_max(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <int NB>
+__device__ __forceinline__ void a64_col_dots(const RegionArgs<double> &a, const ColNL<double> &nl,
+                                             int ncw, const double *pencil) {
+    ColEntry en[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) en[c] = c < nl.ncol ? nl.cols[c] : ColEntry{-1, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        if (c >= ncw) break;   // wave-uniform
+        const ColEntry e = en[c];
+        double s[NP] = {0.0, 0.0, 0.0, 0.0};
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            double ch[NB][NP], v[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);   // a short batch re-reads its last row
+                const double *chp = a.chi + (int64_t)(e.row0 + i) * NP;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
+                v[b] = i0 + b < e.n ? pencil[e.zlo + i] : 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int l = 0; l < NP; ++l) s[l] += ch[b][l] * v[b];
+        }
+        int slot = e.slot;
+        merge_equal_slots<double, NP>(s, slot);
+        if (slot >= 0) {
+            double *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + slot) * NP;
+#pragma unroll
+            for (int l = 0; l < NP; ++l) atomicAdd(&pa[l], s[l]);
+        }
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ void a64_col_update(const RegionArgs<double> &a,
+                                               const ColNL<double> &nl, double *pencil,
+                                               double half) {
+    ColEntry en[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) en[c] = c < nl.ncol ? nl.cols[c] : ColEntry{0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        if (c >= nl.ncol) break;
+        const ColEntry e = en[c];
+        const double *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
+        const double *sc = nl.scale + (int64_t)e.slot * NP;
+        double f[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) f[l] = sc[l] * pa[l] * half;
+        for (int i0 = 0; i0 < e.n; i0 += NB) {
+            double ch[NB][NP];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = min(i0 + b, e.n - 1);
+                const double *chp = a.chi + (int64_t)(e.row0 + i) * NP;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (i0 + b < e.n)
+                    pencil[e.zlo + i0 + b] +=
+                        ch[b][0] * f[0] + ch[b][1] * f[1] + ch[b][2] * f[2] + ch[b][3] * f[3];
+        }
+    }
+}
+
 // One recurrence step with the two live vectors in registers:
 //   v_{k+1} = scale (2 Hs v_k - v_{k-1})  (+ inj at plane inj_z of the owning
 // thread), scale = 1/2 on the first step.  On entry cur = v_k and nw = v_{k-1};
@@ -215,7 +298,7 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
                                          uint32_t plane, int gz0, int n2, double (&cur)[E],
                                          double (&nw)[E], double *lds, ColNL<double> &nl,
                                          bool first, __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
-                                         uint32_t out, int inj_z, double inj) {
+                                         uint32_t out, int inj_z, double inj, int ncw) {
     constexpr int EE = E * E;
     constexpr int DB = A64_DB;
     constexpr int NDB = (E + DB - 1) / DB;
@@ -239,7 +322,7 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
         }
     }
     __syncthreads();
-    if (c.nat) col_dots<double, false, A64_NB>(a, nl, c.mine);
+    if (c.nat) a64_col_dots<A64_NB>(a, nl, ncw, c.mine);
     if (c.active) {
         // an opaque zero keeps the plane offsets from being hoisted out of the
         // step loop
@@ -301,7 +384,7 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
     }
     if (c.nat) {
         if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
-        if (nl.ncol) col_update<double, A64_NB>(a, nl, c.mine, first ? 0.5 : 1.0);
+        if (nl.ncol) a64_col_update<A64_NB>(a, nl, c.mine, first ? 0.5 : 1.0);
         if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
         col_zero_next<double, BLOCK, false>(nl, c.nat);
     }
@@ -417,6 +500,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         ColNL<T> nl{};
         nl.cols = mycols;
         nl.ncol = ncol;
+        const int ncw = a64_wave_max(ncol);   // every lane runs the wave's count (DPP merge)
         nl.pacc = &pacc[0][0][0];
         nl.scale = &pfac[0][0];
         nl.maxat = AT;
@@ -435,7 +519,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
             for (int z = 0; z < E; ++z) a64_st(Sr, svo, (VO + (uint32_t)(z * EE)) * 8u, X[z]);
         for (int k = 0; k + 1 <= K - 1; ++k) {
             a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, k == 0,
-                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0);
+                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0, ncw);
             a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)k * AT * NP);
         }
         // X = v_{K-1}: its projections without a step
@@ -457,7 +541,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         for (int k = K - 1; k >= 1; --k) {
             const T ak = 2.0 * (gr * aa.coef_c[k] + gu * aa.coef_d[k]);
             a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, false,
-                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak);
+                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak, ncw);
             a64_store_proj<BLOCK>(nl, c.nat, Qrow + (int64_t)k * AT * NP);
         }
         // X = vt_1: its projections q_0 without a step
