@@ -81,16 +81,28 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t a64_rsrc(const void *base, int
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n,
                                              A64_RSRC_WORD3);
 }
+// Cache policy of the streams: the slot rows are written once per step and
+// read once in the final passes, so they go non-temporal (their 157 KB per
+// step and workgroup would otherwise evict the diagonal and the projector
+// table, which every step reads again, from the L2).
+constexpr int A64_CACHED = 0;
+#ifndef A64_STREAM_POLICY
+#define A64_STREAM_POLICY 2        // nt
+#endif
+constexpr int A64_STREAM = A64_STREAM_POLICY;
+
 // byte offsets: voff per lane, soff block-uniform
+template <int POL = A64_CACHED>
 __device__ __forceinline__ double a64_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     const a64_u2 v =
-        __builtin_amdgcn_raw_buffer_load_b64(r, voff, __builtin_amdgcn_readfirstlane(soff), 0);
+        __builtin_amdgcn_raw_buffer_load_b64(r, voff, __builtin_amdgcn_readfirstlane(soff), POL);
     return __builtin_bit_cast(double, v);
 }
+template <int POL = A64_STREAM>
 __device__ __forceinline__ void a64_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
                                        double x) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(a64_u2, x), r, voff,
-                                          __builtin_amdgcn_readfirstlane(soff), 0);
+                                          __builtin_amdgcn_readfirstlane(soff), POL);
 }
 
 constexpr int64_t a64_proj_elems(int K) { return (int64_t)K * A64_ATOMS * NP; }
@@ -569,10 +581,10 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
                         if (z0 + i < E) {
                             const uint32_t o0 = (uint32_t)(k * E3 + (z0 + i) * EE);
                             const uint32_t o1 = (uint32_t)(k1 * E3 + (z0 + i) * EE);
-                            tv[0][i] = a64_ld(Sr, svo, (TO + o0) * 8u);
-                            vv[0][i] = a64_ld(Sr, svo, (VO + o0) * 8u);
-                            tv[1][i] = a64_ld(Sr, svo, (TO + o1) * 8u);
-                            vv[1][i] = a64_ld(Sr, svo, (VO + o1) * 8u);
+                            tv[0][i] = a64_ld<A64_STREAM>(Sr, svo, (TO + o0) * 8u);
+                            vv[0][i] = a64_ld<A64_STREAM>(Sr, svo, (VO + o0) * 8u);
+                            tv[1][i] = a64_ld<A64_STREAM>(Sr, svo, (TO + o1) * 8u);
+                            vv[1][i] = a64_ld<A64_STREAM>(Sr, svo, (VO + o1) * 8u);
                         }
                     }
 #pragma unroll
@@ -633,8 +645,8 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
                                 // the lane offset, the step into the scalar one
                                 const uint32_t vo =
                                     (uint32_t)((e.zlo + min(i0 + r, e.n - 1)) * EE + tid) * 8u;
-                                tv[h][r] = a64_ld(Sr, vo, (TO + (uint32_t)(kk * E3)) * 8u);
-                                vv[h][r] = a64_ld(Sr, vo, (VO + (uint32_t)(kk * E3)) * 8u);
+                                tv[h][r] = a64_ld<A64_STREAM>(Sr, vo, (TO + (uint32_t)(kk * E3)) * 8u);
+                                vv[h][r] = a64_ld<A64_STREAM>(Sr, vo, (VO + (uint32_t)(kk * E3)) * 8u);
                             }
                         }
 #pragma unroll
