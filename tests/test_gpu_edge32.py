@@ -43,8 +43,9 @@ def test_edge32_forward_gauss_force_fp32():
     mu_ref = O.moments(prob, lmin, lmax, nodes=nodes)
     assert np.abs(mu - mu_ref).max() <= 1e-5
     f_ref = O.cc_nonlocal_force(prob, lmin, lmax, lf, nodes=nodes)
-    if np.abs(f_ref).max() > 0:
-        assert np.abs(f - f_ref).max() <= 1e-4 * np.abs(f_ref).max()
+    # two of the four atoms have supports crossing these boxes (max |f| = 0.26 on the CPU)
+    assert np.abs(f_ref).max() > 1e-2
+    assert np.abs(f - f_ref).max() <= 1e-4 * np.abs(f_ref).max()
     lam_ref, w_ref = O.gauss_rules(prob, lmin, lmax, prob.order, nodes=nodes)
     tau = 0.5 * (lmax - lmin)
     assert np.abs(lam - lam_ref).max() <= 1e-5 * tau
