@@ -79,13 +79,16 @@ typedef struct {
                          /* else 10                                                    */
     int32_t adjoint_precision;  /* sq_precision of sq_density_backward (default 0 =  */
                          /* SQ_FP64: the gradient sums cancel strongly, so FP32      */
-                         /* vectors lose ~1e-4 relative at K ~ 80; FP64 adjoint      */
-                         /* supports region edges <= 21, FP32 adjoint edges <= 27)   */
+                         /* vectors lose ~1e-4 relative at K ~ 80); both support     */
+                         /* region edges <= 27 (FP64 at edge 27: V grids of at most  */
+                         /* 2^29 points)                                             */
     int32_t tune;        /* launch plan when regions fall in several edge buckets   */
-                         /* (9, 13, 17, 21, 27, 32): 0 = sq_setup times one launch   */
-                         /* at the largest bucket against one launch per bucket on   */
-                         /* a sample of the regions and keeps the faster (cached per */
-                         /* geometry in the process); 1 = one launch per bucket;     */
+                         /* (9, 13, 17, 21, 27, 32): 0 = sq_setup times, on a sample */
+                         /* of the regions, one launch at the largest bucket against */
+                         /* one launch per bucket, each launch at 1, 1/2 and 1/4 of  */
+                         /* its occupancy limit of resident workgroups per CU, and   */
+                         /* keeps the fastest (cached per geometry in the process);  */
+                         /* 1 = one launch per bucket at the occupancy limit;        */
                          /* 2 = one launch of one workgroup per region (the plain,   */
                          /* unbatched path, kept as the baseline of the batching)    */
 } sq_params;
@@ -116,7 +119,7 @@ typedef struct {
     int64_t region_points;  /* sum over nodes of the region size |R_q|                 */
     int64_t workspace_bytes;/* device memory held by the context                       */
     int32_t n_launches;     /* persistent region launches per pass (the launch plan)   */
-    int32_t pad_;
+    int32_t forward_blocks; /* resident forward workgroups summed over those launches  */
     int64_t n_force_nodes;  /* nodes inside some projector support (sq_nonlocal_force) */
     int64_t force_region_points; /* sum of their region sizes                          */
 } sq_info;

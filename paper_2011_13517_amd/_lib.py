@@ -54,7 +54,7 @@ class sq_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("order", C.c_int32), ("vgrid", C.c_int32 * 3),
                 ("n_atoms", C.c_int32), ("max_region", C.c_int32 * 3),
                 ("region_points", C.c_int64), ("workspace_bytes", C.c_int64),
-                ("n_launches", C.c_int32), ("pad_", C.c_int32),
+                ("n_launches", C.c_int32), ("forward_blocks", C.c_int32),
                 ("n_force_nodes", C.c_int64), ("force_region_points", C.c_int64)]
 
 

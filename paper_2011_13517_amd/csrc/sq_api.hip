@@ -89,6 +89,7 @@ struct Group {
     int begin = 0, count = 0;
     int grid_fwd = 1, grid_adj = 1;
     int grid_gauss = 0;   // set on the first Gauss sweep
+    int bpc = 0;          // resident forward workgroups per CU (0: the occupancy limit)
 };
 enum { PLAN_MERGED = 0, PLAN_SPLIT = 1, PLAN_PER_REGION = 2 };
 
@@ -131,9 +132,22 @@ static std::vector<Group> make_groups(const std::vector<Item> &items, int plan) 
     return g;
 }
 
-// plans measured by the tuner, per geometry (process-wide)
+// plans measured by the tuner, per geometry (process-wide): the plan and the
+// resident forward workgroups per CU of each edge bucket
+struct TuneChoice {
+    int plan = 1;
+    std::map<int, int> bpc;
+};
 static std::mutex g_tune_mu;
-static std::map<std::string, int> g_tune_cache;
+static std::map<std::string, TuneChoice> g_tune_cache;
+
+// persistent grid of a group: its resident workgroups per CU (the occupancy
+// limit, or the tuner's smaller choice) times the CUs, at most one per region
+static void set_forward_grid(int prec, int r, int ncu, Group &g) {
+    const int occ = forward_blocks_per_cu(prec, g.E, r, g.maskz);
+    const int b = g.bpc > 0 ? std::min(g.bpc, occ) : occ;
+    g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)b * ncu, g.count));
+}
 
 struct sq_ctx {
     sq_params p{};
@@ -149,7 +163,8 @@ struct sq_ctx {
     int aprec = 0;   // precision of the adjoint
     int E = 0;                    // largest edge bucket of the work list
     std::vector<Group> groups;    // launch plan: one persistent launch per group
-    int plan = 0;                 // PLAN_MERGED or PLAN_SPLIT
+    int plan = 0;                 // PLAN_MERGED, PLAN_SPLIT or PLAN_PER_REGION
+    std::map<int, int> tuned_bpc; // tuner: resident forward workgroups per CU, by edge bucket
     int max_region[3] = {};
     int64_t region_points = 0;
     int64_t bytes = 0;
@@ -350,26 +365,34 @@ sq_status run_forward(const sq_ctx &c, const std::vector<Group> &groups, const I
                              : run_forward_t<float>(c, groups, items, mu, st);
 }
 
-// Launch-plan tuner: times the merged and the split plan of the work list on
-// an evenly strided sample of at most 8192 regions (same bucket mix), with a
-// zero potential (the cost does not depend on the values), and keeps the
-// faster.  Results are cached per geometry key for the process.
+// Launch-plan tuner.  On an evenly strided sample of at most 8192 regions
+// (same bucket mix), with a zero potential (the cost does not depend on the
+// values), it times for every launch group of the merged and of the split plan
+// the persistent grid at the occupancy limit and at one half and one quarter
+// of it (fewer resident workgroups per CU trade latency hiding for less
+// contention on the LDS, L2 and the work counter), keeps each group's fastest
+// grid, and then the plan whose groups sum to less.  The choice (plan and
+// workgroups per CU of each edge bucket) is cached per geometry key, which
+// includes the CU count and each bucket's occupancy limit, for the process.
 sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
     std::string key;
     {
         std::map<int, int64_t> hist;
         for (const Item &it : items) hist[item_bucket(it)] += 1;
         char buf[160];
-        std::snprintf(buf, sizeof buf, "p%d r%d K%d a%d n%d bc%d", c.prec, c.r, c.K, c.n_atoms,
-                      (int)items.size(), c.p.bc);
+        std::snprintf(buf, sizeof buf, "p%d r%d K%d a%d n%d bc%d cu%d", c.prec, c.r, c.K,
+                      c.n_atoms, (int)items.size(), c.p.bc, ncu);
         key = buf;
-        for (auto &kv : hist) key += " " + std::to_string(kv.first) + ":" + std::to_string(kv.second);
+        for (auto &kv : hist)
+            key += " " + std::to_string(kv.first) + ":" + std::to_string(kv.second) + "/" +
+                   std::to_string(forward_blocks_per_cu(c.prec, kv.first, c.r, true));
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto f = g_tune_cache.find(key);
         if (f != g_tune_cache.end()) {
-            c.plan = f->second;
+            c.plan = f->second.plan;
+            c.tuned_bpc = f->second.bpc;
             return SQ_OK;
         }
     }
@@ -385,16 +408,9 @@ sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
     if (hipMalloc(reinterpret_cast<void **>(&d_sample), sample.size() * sizeof(Item)) != hipSuccess)
         return fail(SQ_ERR_OOM, "tuner: hipMalloc failed");
     std::vector<Group> plans[2] = {make_groups(sample, PLAN_MERGED), make_groups(sample, PLAN_SPLIT)};
-    for (auto &gs : plans)
-        for (Group &g : gs) {
-            const int occ = forward_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
-            g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
-        }
     Scalars s{};
     s.omega = 0.0;
     s.tau = 1.0;
-    float best = -1.0f;
-    int best_plan = PLAN_SPLIT;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     sq_status st = SQ_OK;
     if (hipMemcpy(d_sample, sample.data(), sample.size() * sizeof(Item), hipMemcpyHostToDevice) !=
@@ -405,19 +421,48 @@ sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         st = fail(SQ_ERR_HIP, "tuner setup failed");
     }
+    // one group at one grid: an untimed run (first grid only), then a timed one
+    auto time_group = [&](const Group &g, bool warm, float *ms) -> sq_status {
+        const std::vector<Group> one{g};
+        sq_status t = SQ_OK;
+        if (warm) t = run_forward(c, one, d_sample, c.d_mu, nullptr);
+        if (t == SQ_OK && hipEventRecord(e0, nullptr) != hipSuccess) t = fail(SQ_ERR_HIP, "event");
+        if (t == SQ_OK) t = run_forward(c, one, d_sample, c.d_mu, nullptr);
+        if (t == SQ_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+            t = fail(SQ_ERR_HIP, "tuner timing failed");
+        return t;
+    };
+    float best = -1.0f;
+    TuneChoice choice;
     for (int pl = 0; pl < 2 && st == SQ_OK; ++pl) {
-        // one untimed run, then one timed
-        st = run_forward(c, plans[pl], d_sample, c.d_mu, nullptr);
-        if (st == SQ_OK && hipEventRecord(e0, nullptr) != hipSuccess) st = fail(SQ_ERR_HIP, "event");
-        if (st == SQ_OK) st = run_forward(c, plans[pl], d_sample, c.d_mu, nullptr);
-        float ms = 0.0f;
-        if (st == SQ_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
-                            hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            st = fail(SQ_ERR_HIP, "tuner timing failed");
-        if (st == SQ_OK && (best < 0.0f || ms < best)) {
-            best = ms;
-            best_plan = pl == 0 ? PLAN_MERGED : PLAN_SPLIT;
+        float total = 0.0f;
+        std::map<int, int> bpc;
+        for (Group &g : plans[pl]) {
+            const int occ = forward_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
+            float gbest = -1.0f;
+            int gb = occ;
+            for (int b : {occ, occ / 2, occ / 4}) {
+                if (st != SQ_OK || b < 1 || (b != occ && b == gb)) continue;
+                if (b != occ && (int64_t)b * ncu >= g.count && (int64_t)gb * ncu >= g.count)
+                    continue;   // both grids already cover every region of the group
+                g.bpc = b;
+                set_forward_grid(c.prec, c.r, ncu, g);
+                float ms = 0.0f;
+                st = time_group(g, b == occ, &ms);
+                if (st == SQ_OK && (gbest < 0.0f || ms < gbest)) {
+                    gbest = ms;
+                    gb = b;
+                }
+            }
+            total += gbest > 0.0f ? gbest : 0.0f;
+            bpc[g.E] = gb;
+        }
+        if (st == SQ_OK && (best < 0.0f || total < best)) {
+            best = total;
+            choice.plan = pl == 0 ? PLAN_MERGED : PLAN_SPLIT;
+            choice.bpc = bpc;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -428,9 +473,10 @@ sq_status tune_plan(sq_ctx &c, const std::vector<Item> &items, int ncu) {
         hipMemset(c.d_status, 0, sizeof(int32_t)) != hipSuccess)
         return fail(SQ_ERR_HIP, "tuner reset failed");
     if (st != SQ_OK) return st;
-    c.plan = best_plan;
+    c.plan = choice.plan;
+    c.tuned_bpc = choice.bpc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best_plan;
+    g_tune_cache[key] = choice;
     return SQ_OK;
 }
 
@@ -812,8 +858,9 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
     // split plan is used whenever there is more than one bucket.
     auto grids = [&](std::vector<Group> &gs) {
         for (Group &g : gs) {
-            const int occ = forward_blocks_per_cu(c.prec, g.E, c.r, g.maskz);
-            g.grid_fwd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * ncu, g.count));
+            auto f = c.tuned_bpc.find(g.E);
+            g.bpc = f != c.tuned_bpc.end() ? f->second : 0;
+            set_forward_grid(c.prec, c.r, ncu, g);
         }
     };
     std::vector<Group> merged = make_groups(items, PLAN_MERGED);
@@ -832,6 +879,7 @@ sq_status sq_setup(const sq_params *params, const sq_projectors *proj, const int
             if (ts != SQ_OK) return bail(ts);
         }
         c.groups = c.plan == PLAN_SPLIT ? split : merged;
+        grids(c.groups);   // the tuner's workgroups per CU, when it ran
     }
 
     // nonlocal force work list: nodes where some chi_Jlm is nonzero, one
@@ -947,7 +995,8 @@ sq_status sq_get_info(const sq_ctx *ctx, sq_info *info) {
     info->region_points = ctx->region_points;
     info->workspace_bytes = ctx->bytes;
     info->n_launches = (int32_t)ctx->groups.size();
-    info->pad_ = 0;
+    info->forward_blocks = 0;
+    for (const Group &g : ctx->groups) info->forward_blocks += g.grid_fwd;
     info->n_force_nodes = ctx->n_force_nodes;
     info->force_region_points = ctx->force_region_points;
     return SQ_OK;
