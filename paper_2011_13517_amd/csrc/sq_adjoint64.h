@@ -40,6 +40,7 @@
 //    and added once per atom per region.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "sq_region.h"
@@ -60,6 +61,9 @@ constexpr int A64_ATOMS = 48;      // atoms per box (the LDS left beside the FP6
 constexpr int A64_DB = 9;          // planes of the diagonal per load batch
 #ifndef A64_NB
 #define A64_NB 2                   // support rows per load batch of the projector block
+#endif
+#ifndef A64_FZB
+#define A64_FZB 3                  // planes per batch of the final dV / dR pass
 #endif
 #ifndef A64_XY_SPLIT
 #define A64_XY_SPLIT 3             // x/y pipeline units per pencil (0: plain loop)
@@ -89,7 +93,11 @@ constexpr int A64_CACHED = 0;
 #ifndef A64_STREAM_POLICY
 #define A64_STREAM_POLICY 2        // nt
 #endif
+#ifndef A64_REREAD_POLICY
+#define A64_REREAD_POLICY 2        // nt
+#endif
 constexpr int A64_STREAM = A64_STREAM_POLICY;
+constexpr int A64_REREAD = A64_REREAD_POLICY;   // the final passes' reads of the rows
 
 // byte offsets: voff per lane, soff block-uniform
 template <int POL = A64_CACHED>
@@ -561,121 +569,164 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         a64_store_proj<BLOCK>(nl, c.nat, Qrow);
         __syncthreads();   // the slot's projection rows are read by other threads below
 
-        // ---- dV: G(z) = sum_k alpha_k vt_{k+1}(z) v_k(z), own pencil, FP64 ----
-        if (aa.dV && c.active) {
-            constexpr int ZB = 9;   // planes per pass (loads in flight vs registers)
-            const double itau = 1.0 / tau;
-#pragma unroll
-            for (int z0 = 0; z0 < E; z0 += ZB) {
-                T G[ZB];
-#pragma unroll
-                for (int i = 0; i < ZB; ++i) G[i] = 0.0;
-                // two steps per iteration: 4 ZB loads in flight
-                for (int k = 0; k < K; k += 2) {
-                    const bool two = k + 1 < K;
-                    const int k1 = two ? k + 1 : k;
-                    const T a0 = k == 0 ? 1.0 : 2.0, a1 = two ? 2.0 : 0.0;
-                    T tv[2][ZB], vv[2][ZB];
-#pragma unroll
-                    for (int i = 0; i < ZB; ++i) {
-                        if (z0 + i < E) {
-                            const uint32_t o0 = (uint32_t)(k * E3 + (z0 + i) * EE);
-                            const uint32_t o1 = (uint32_t)(k1 * E3 + (z0 + i) * EE);
-                            tv[0][i] = a64_ld<A64_STREAM>(Sr, svo, (TO + o0) * 8u);
-                            vv[0][i] = a64_ld<A64_STREAM>(Sr, svo, (VO + o0) * 8u);
-                            tv[1][i] = a64_ld<A64_STREAM>(Sr, svo, (TO + o1) * 8u);
-                            vv[1][i] = a64_ld<A64_STREAM>(Sr, svo, (VO + o1) * 8u);
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < ZB; ++i) {
-                        if (z0 + i < E) {
-                            G[i] = fma(a0 * tv[0][i], vv[0][i], G[i]);
-                            G[i] = fma(a1 * tv[1][i], vv[1][i], G[i]);
-                        }
-                    }
+        // ---- final pass: dV and dR from the stored rows ----
+        // Every lane streams its own pencil's rows plane by plane (one plane of
+        // all lanes is one contiguous slot row, so the loads coalesce) in
+        // batches of A64_FZB planes over all k, and accumulates
+        //   G(z)   = sum_k alpha_k vt_{k+1}(z) v_k(z)                    (dV)
+        //   W_l(z) = sum_k alpha_k (p_k,l vt_{k+1}(z) + q_k,l v_k(z))   (dR)
+        // for the planes of the batch and (W) up to two of its column entries
+        // at a time; a batch's W rows that lie in an entry's support piece are
+        // contracted with dchi at once.  p_k and q_k of the box's atoms are read
+        // from the idle LDS box when they fit it, else from the slot.
+        const bool want_dV = aa.dV != nullptr, want_dR = aa.dR != nullptr;
+        if (want_dV || want_dR) {
+            const int pq = K * c.nat * NP;
+            const bool staged = want_dR && 2 * (int64_t)pq <= (int64_t)region_lds_elems<T, E>();
+            if (staged) {
+                for (int i = tid; i < pq; i += BLOCK) {
+                    const int k = i / (c.nat * NP), rest = i - k * (c.nat * NP);
+                    lds[i] = Prow[(int64_t)k * AT * NP + rest];
+                    lds[pq + i] = Qrow[(int64_t)k * AT * NP + rest];
                 }
-                // this batch of planes is complete: to the grid
-#pragma unroll
-                for (int i = 0; i < ZB; ++i) {
-                    const int z = z0 + i;
-                    if (z < E && z < c.dz) {
-                        int gz = gz0 + z;
-                        gz = gz >= n2 ? gz - n2 : gz;
-                        unsafeAtomicAdd(aa.dV + col + plane * gz, G[i] * itau);
-                    }
-                }
-            }
-        }
-
-        // ---- dR: row accumulators W on this pencil's support rows ----
-        if (aa.dR) {
-            constexpr int RB = 4;   // rows per pass
-            for (int cc = 0; cc < nl.ncol; ++cc) {
-                const ColEntry e = mycols[cc];
-                const double *cj = a.cJ + (int64_t)slots[e.slot].atom * NP;
-                double sx[3] = {0.0, 0.0, 0.0};
-                for (int i0 = 0; i0 < e.n; i0 += RB) {
-                    double W[RB][NP];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int l = 0; l < NP; ++l) W[r][l] = 0.0;
-                    for (int k = 0; k < K; k += 2) {
-                        // two steps per iteration (the second weighted 0 past K - 1)
-                        const bool two = k + 1 < K;
-                        const int k1 = two ? k + 1 : k;
-                        const T al[2] = {k == 0 ? 1.0 : 2.0, two ? 2.0 : 0.0};
-                        double p[2][NP], q[2][NP], tv[2][RB], vv[2][RB];
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int kk = h ? k1 : k;
-                            const double *pk = Prow + ((int64_t)kk * AT + e.slot) * NP;
-                            const double *qk = Qrow + ((int64_t)kk * AT + e.slot) * NP;
-#pragma unroll
-                            for (int l = 0; l < NP; ++l) {
-                                p[h][l] = pk[l];
-                                q[h][l] = qk[l];
-                            }
-                            // z differs between lanes here (each lane's own piece),
-                            // so the row address is a per-lane one
-#pragma unroll
-                            for (int r = 0; r < RB; ++r) {
-                                // z differs between lanes: the plane goes into
-                                // the lane offset, the step into the scalar one
-                                const uint32_t vo =
-                                    (uint32_t)((e.zlo + min(i0 + r, e.n - 1)) * EE + tid) * 8u;
-                                tv[h][r] = a64_ld<A64_STREAM>(Sr, vo, (TO + (uint32_t)(kk * E3)) * 8u);
-                                vv[h][r] = a64_ld<A64_STREAM>(Sr, vo, (VO + (uint32_t)(kk * E3)) * 8u);
-                            }
-                        }
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-#pragma unroll
-                            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                                for (int l = 0; l < NP; ++l)
-                                    W[r][l] += al[h] * (p[h][l] * tv[h][r] + q[h][l] * vv[h][r]);
-                    }
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        if (i0 + r < e.n) {
-                            const double *dc = a.dchi + (int64_t)(e.row0 + i0 + r) * 3 * NP;
-#pragma unroll
-                            for (int l = 0; l < NP; ++l)
-#pragma unroll
-                                for (int x = 0; x < 3; ++x) sx[x] += cj[l] * dc[l * 3 + x] * W[r][l];
-                        }
-                    }
-                }
-                const double hs = a.h3 / tau;
-#pragma unroll
-                for (int x = 0; x < 3; ++x) atomicAdd(&cdR[e.slot][x], sx[x] * hs);
             }
             __syncthreads();
-            for (int j = tid; j < c.nat; j += BLOCK)
-                for (int x = 0; x < 3; ++x)
-                    unsafeAtomicAdd(aa.dR + (int64_t)slots[j].atom * 3 + x, cdR[j][x]);
+            const double itau = 1.0 / tau, hs = a.h3 / tau;
+            auto final_pass = [&](auto staged_tag) {
+                constexpr bool ST = decltype(staged_tag)::value;
+                constexpr int ZB = A64_FZB, WC = 2;
+                const int pstride = ST ? c.nat : AT;
+                const int npass = want_dR ? max(1, (ncw + WC - 1) / WC) : 1;
+                for (int pass = 0; pass < npass; ++pass) {
+                    const bool do_g = want_dV && pass == 0;
+                    ColEntry en[WC];
+                    bool has[WC];
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) {
+                        const int ci = pass * WC + w;
+                        has[w] = want_dR && ci < nl.ncol;
+                        en[w] = has[w] ? mycols[ci] : ColEntry{0, 0, 0, 0};
+                    }
+                    double sx[WC][3];
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) sx[w][0] = sx[w][1] = sx[w][2] = 0.0;
+                    for (int z0 = 0; z0 < E; z0 += ZB) {
+                        bool ov[WC], wov[WC];
+                        bool any_w = false;
+#pragma unroll
+                        for (int w = 0; w < WC; ++w) {
+                            ov[w] = has[w] && en[w].zlo < z0 + ZB && en[w].zlo + en[w].n > z0;
+                            wov[w] = __any(ov[w]) != 0;   // wave-uniform
+                            any_w = any_w || wov[w];
+                        }
+                        if (!do_g && !any_w) continue;
+                        double G[ZB], W[WC][ZB][NP];
+#pragma unroll
+                        for (int i = 0; i < ZB; ++i) G[i] = 0.0;
+#pragma unroll
+                        for (int w = 0; w < WC; ++w)
+#pragma unroll
+                            for (int i = 0; i < ZB; ++i)
+#pragma unroll
+                                for (int l = 0; l < NP; ++l) W[w][i][l] = 0.0;
+                        for (int k = 0; k < K; k += 2) {
+                            // two steps per iteration (the second weighted 0 past K - 1)
+                            const bool two = k + 1 < K;
+                            const int k1 = two ? k + 1 : k;
+                            const T al[2] = {k == 0 ? 1.0 : 2.0, two ? 2.0 : 0.0};
+                            double tv[2][ZB], vv[2][ZB];
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int kk = h ? k1 : k;
+#pragma unroll
+                                for (int i = 0; i < ZB; ++i) {
+                                    const uint32_t o = (uint32_t)(kk * E3 + min(z0 + i, E - 1) * EE);
+                                    tv[h][i] = a64_ld<A64_REREAD>(Sr, svo, (TO + o) * 8u);
+                                    vv[h][i] = a64_ld<A64_REREAD>(Sr, svo, (VO + o) * 8u);
+                                }
+                            }
+                            if (do_g) {
+#pragma unroll
+                                for (int i = 0; i < ZB; ++i) {
+                                    G[i] = fma(al[0] * tv[0][i], vv[0][i], G[i]);
+                                    G[i] = fma(al[1] * tv[1][i], vv[1][i], G[i]);
+                                }
+                            }
+#pragma unroll
+                            for (int w = 0; w < WC; ++w) {
+                                if (!wov[w]) continue;
+                                double pk[2][NP], qk[2][NP];
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) {
+                                    const int64_t o =
+                                        ((int64_t)(h ? k1 : k) * pstride + en[w].slot) * NP;
+#pragma unroll
+                                    for (int l = 0; l < NP; ++l) {
+                                        if constexpr (ST) {
+                                            pk[h][l] = lds[o + l];
+                                            qk[h][l] = lds[pq + o + l];
+                                        } else {
+                                            pk[h][l] = Prow[o + l];
+                                            qk[h][l] = Qrow[o + l];
+                                        }
+                                    }
+                                }
+#pragma unroll
+                                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                    for (int i = 0; i < ZB; ++i)
+#pragma unroll
+                                        for (int l = 0; l < NP; ++l)
+                                            W[w][i][l] += al[h] * (pk[h][l] * tv[h][i] +
+                                                                   qk[h][l] * vv[h][i]);
+                            }
+                        }
+                        if (do_g && c.active) {
+#pragma unroll
+                            for (int i = 0; i < ZB; ++i) {
+                                const int z = z0 + i;
+                                if (z < E && z < c.dz) {
+                                    int gz = gz0 + z;
+                                    gz = gz >= n2 ? gz - n2 : gz;
+                                    unsafeAtomicAdd(aa.dV + col + plane * gz, G[i] * itau);
+                                }
+                            }
+                        }
+                        // rows of this batch inside an entry's support piece
+#pragma unroll
+                        for (int w = 0; w < WC; ++w) {
+                            if (!ov[w]) continue;
+                            const double *cj = a.cJ + (int64_t)slots[en[w].slot].atom * NP;
+#pragma unroll
+                            for (int i = 0; i < ZB; ++i) {
+                                const int z = z0 + i;
+                                if (z >= en[w].zlo && z < en[w].zlo + en[w].n) {
+                                    const double *dc =
+                                        a.dchi + (int64_t)(en[w].row0 + z - en[w].zlo) * 3 * NP;
+#pragma unroll
+                                    for (int l = 0; l < NP; ++l)
+#pragma unroll
+                                        for (int x = 0; x < 3; ++x)
+                                            sx[w][x] += cj[l] * dc[l * 3 + x] * W[w][i][l];
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < WC; ++w)
+                        if (has[w])
+#pragma unroll
+                            for (int x = 0; x < 3; ++x) atomicAdd(&cdR[en[w].slot][x], sx[w][x] * hs);
+                }
+            };
+            if (staged) final_pass(std::true_type{});
+            else final_pass(std::false_type{});
+            if (want_dR) {
+                __syncthreads();
+                for (int j = tid; j < c.nat; j += BLOCK)
+                    for (int x = 0; x < 3; ++x)
+                        unsafeAtomicAdd(aa.dR + (int64_t)slots[j].atom * 3 + x, cdR[j][x]);
+            }
         }
         __syncthreads();
     }

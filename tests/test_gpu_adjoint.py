@@ -207,11 +207,11 @@ def test_adjoint_config5_embedded_nodes():
     assert rel(dV, gV) < 1e-10 and rel(dRg, dR) < 1e-10
 
 
-@pytest.mark.parametrize("order", [11, 12])
+@pytest.mark.parametrize("order", [1, 2, 11, 12])
 def test_fp64_adjoint_edge27_clipped_boxes(order):
     """The FP64 edge-27 kernel on ragged Dirichlet-clipped boxes (edges 14..27 per
-    axis, some in the 27 bucket with dz < 27), odd and even K, dV + dR and dV
-    alone, against the oracle at 1e-10."""
+    axis, some in the 27 bucket with dz < 27), K = 1 (no recurrence step), K = 2
+    (one), odd and even K, dV + dR and dV alone, against the oracle at 1e-10."""
     print(f"[case] FP64 adjoint edge27 clipped K={order}", flush=True)
     prob = synth.small_problem(81, n=(30, 28, 32), h=(0.5, 0.5, 0.5), bc=synth.BC_DIRICHLET,
                                rcut=(13, 13, 13), n_atoms=6, rc=1.4, order=order, kT=0.2,
