@@ -313,8 +313,10 @@ def config(c: int) -> Problem:
     raise ValueError(f"unknown config {c}")
 
 
-# lambda_f used by the uneven-region workload, which has no electron count of its own
-FIXED_LAMBDA_F_C3 = -0.10
+# lambda_f used by the uneven-region workload, which has no electron count of its
+# own: the FP64 Fermi level of the 64^3 workload (config 2), computed by the oracle
+# alone over all of its nodes (tests/golden/make_c2_lambda_f.py -> c2_lambda_f.txt)
+FIXED_LAMBDA_F_C3 = 0.09726053266210105
 
 
 def _config5(rng):
