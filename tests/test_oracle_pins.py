@@ -951,3 +951,17 @@ def test_cc_force_equals_minus_grand_potential_gradient_full_trace():
     _, dR = O.adjoint(p2, lmin, lmax, a)
     assert np.abs(f_cc).max() > 1e-4
     assert np.abs(f_cc + dR).max() <= 1e-11 * np.abs(f_cc).max(), np.abs(f_cc + dR).max()
+
+
+def test_uneven_workload_lambda_f_is_the_stored_oracle_level():
+    """The uneven-region workload's fixed lambda_f is the oracle's FP64 Fermi level
+    of the 64^3 workload as written by tests/golden/make_c2_lambda_f.py, and that
+    level lies inside the spectral bounds the script used."""
+    path = os.path.join(GOLD, "c2_lambda_f.txt")
+    with open(path) as f:
+        lines = [l for l in f if l.strip()]
+    bounds = [float(x) for x in lines[1].split("bounds")[1].split(";")[0].split()]
+    lf = float(lines[-1])
+    assert synth.FIXED_LAMBDA_F_C3 == lf
+    assert synth.config(3).lambda_f == lf
+    assert bounds[0] < lf < bounds[1]
