@@ -246,3 +246,69 @@ def test_graph_replay_config3_split_plan():
                                node_m=prob.node_rcut[pick])
             assert np.abs(got[0].cpu().numpy()[pick] - mu_ref).max() < K * 2.0 ** -24 * 8
     ctx.close()
+
+
+def test_graph_replay_edge27_fp64_adjoint():
+    """The benchmarked sequence on 512 random nodes of the 64^3 workload (27^3
+    regions, r = 6, 96 atoms, K = 100): device bounds + FP32 forward + Fermi
+    level (fixed lambda_f) + the FP64 edge-27 adjoint (dV, dR), captured once and
+    replayed with new potentials; every replay against an eager run on the same
+    input (the adjoint itself is held to the oracle in test_gpu_adjoint.py)."""
+    from paper_2011_13517_amd import sq
+    print("[case] graph replay edge27 fp64 adjoint", flush=True)
+    prob = synth.config(2)
+    rng = np.random.default_rng(27)
+    nodes = np.sort(rng.choice(prob.n_nodes, 512, replace=False)).astype(np.int64)
+    ctx = sq.Context(prob, precision=1, nodes=nodes, adjoint_precision=0, ckpt_every=1)
+    assert tuple(ctx.info.max_region) == (27, 27, 27)
+    dev = torch.device("cuda")
+    n, K = ctx.n_nodes, ctx.K
+    V0 = torch.tensor(prob.V, dtype=torch.float64, device=dev)
+    V = V0.clone()
+    mu = torch.empty((n, K + 1), dtype=torch.float64, device=dev)
+    M = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    lam = torch.tensor([0.0973], dtype=torch.float64, device=dev)
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    tot = torch.empty(8, dtype=torch.float64, device=dev)
+    g_rho = torch.tensor(rng.normal(size=n), dtype=torch.float64, device=dev)
+    g_u = torch.tensor(rng.normal(size=n), dtype=torch.float64, device=dev)
+    dV = torch.zeros_like(V)
+    dR = torch.zeros((prob.n_atoms, 3), dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.density(V, math.nan, math.nan, moments=mu, moment_sum=M)
+        ctx.fermi_level(max_iter=0, lambda_f=lam, rho=rho, u=u, totals=tot)
+        dV.zero_()
+        dR.zero_()
+        ctx.backward(g_rho, g_u, dV, dR)
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return [t.clone() for t in (mu, rho, u, dV, dR)]
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        pert = 0.0 if rep == 0 else 0.05
+        V.copy_(V0 + torch.tensor(rng.uniform(-pert, pert, size=prob.V.shape), device=dev))
+        graph.replay()
+        got = snapshot()
+        step()
+        ref = snapshot()
+        assert ctx.status() == 0
+        # projections and dV / dR are reduced with atomics (order may differ);
+        # a stale input would differ by O(0.05)
+        for i, (a, b) in enumerate(zip(got, ref)):
+            tol = 2e-5 if i < 3 else 1e-11
+            scale = max(b.abs().max().item(), 1e-300)
+            assert (a - b).abs().max().item() <= tol * scale, (rep, i)
+        assert dR.abs().max().item() > 0
+    ctx.close()
