@@ -16,10 +16,12 @@
 //  * Thread t owns the z-pencil (t mod dx, t / dx) of the two live vectors in
 //    VGPRs; the LDS holds the box once (x/y neighbours) plus one zero pencil,
 //    and the per-atom projections.
-//  * Projector block on the column path of the other region kernels (each
-//    thread projects its own pencil's pieces of the atom supports and adds the
-//    rank-4 term to its own pencil); the atom list and the column entries of the
-//    box live in the workgroup's HBM slot instead of the LDS.
+//  * Projector block atom-major: at region start the box's support rows are
+//    listed atom by atom in chunks of 64 (row, LDS offset) entries; in every
+//    step each wave walks its share of the chunks, forming chi . v with wave
+//    reductions and adding the rank-4 term with LDS atomics.  The atom list,
+//    the row list and the column entries of the box (used by the final pass)
+//    live in the workgroup's HBM slot instead of the LDS.
 //  * Forward sweep: v_0 .. v_{K-1} go to the slot, and the projections
 //    p_k = chi . v_k that the recurrence forms anyway.  Reverse sweep: vt_{k+1}
 //    goes to the slot, and q_k = chi . vt_{k+1}.  No dchi projections are
@@ -59,14 +61,14 @@ __device__ __forceinline__ double uniform_f64(double x) {
 constexpr int A64_EDGE = 27;
 constexpr int A64_ATOMS = 48;      // atoms per box (the LDS left beside the FP64 box)
 constexpr int A64_DB = 9;          // planes of the diagonal per load batch
-#ifndef A64_NB
-#define A64_NB 2                   // support rows per load batch of the projector block
-#endif
 #ifndef A64_FZB
 #define A64_FZB 3                  // planes per batch of the final dV / dR pass
 #endif
 #ifndef A64_XY_SPLIT
 #define A64_XY_SPLIT 3             // x/y pipeline units per pencil (0: plain loop)
+#endif
+#ifndef A64_NCB
+#define A64_NCB 2                  // chunks per load batch of the atom-major block
 #endif
 // V grids up to this many points keep every byte offset of the diagonal in 32 bits
 // (slot rows: K up to 512 keeps 2 K E^3 doubles below 2^32 bytes)
@@ -114,9 +116,16 @@ __device__ __forceinline__ void a64_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 }
 
 constexpr int64_t a64_proj_elems(int K) { return (int64_t)K * A64_ATOMS * NP; }
+// per-workgroup tables behind the rows: atom slots, column entries, the
+// atom-major list of the box's support rows (int2, at most one entry per
+// column-entry row plus a chunk of padding per atom) and its per-atom counts
+constexpr int64_t a64_list_cap_elems(int E) {
+    return (int64_t)((E * E + 63) / 64 * 64) * MAXC * E + (int64_t)A64_ATOMS * 64;
+}
 constexpr int64_t a64_tables_elems(int E) {
     return ((int64_t)A64_ATOMS * sizeof(Slot) +
-            (int64_t)((E * E + 63) / 64 * 64) * MAXC * sizeof(ColEntry) + 7) / 8;
+            (int64_t)((E * E + 63) / 64 * 64) * MAXC * sizeof(ColEntry) +
+            a64_list_cap_elems(E) * 8 + (int64_t)A64_ATOMS * 4 + 7) / 8;
 }
 constexpr int64_t a64_slot_elems(int K, int E) {
     return round_np(2 * (int64_t)K * E * E * E + 2 * a64_proj_elems(K) + a64_tables_elems(E));
@@ -215,85 +224,223 @@ __device__ __forceinline__ void a64_xy(double (&acc)[E], const StepCtx<double, E
     }
 }
 
-// Projector block of the FP64 kernel (column path, as col_dots / col_update
-// in sq_region.h) with the per-region constants taken out of the step: the
-// wave's largest column count ncw is formed once per region, and the (at most
-// MAXC) column entries of a lane are loaded in one batch at the start of each
-// routine instead of one dependent round trip per entry.
+// the wave's largest column-entry count (the final pass runs every lane to it)
 __device__ __forceinline__ int a64_wave_max(int v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-template <int NB>
-__device__ __forceinline__ void a64_col_dots(const RegionArgs<double> &a, const ColNL<double> &nl,
-                                             int ncw, const double *pencil) {
-    ColEntry en[MAXC];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) en[c] = c < nl.ncol ? nl.cols[c] : ColEntry{-1, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-        if (c >= ncw) break;   // wave-uniform
-        const ColEntry e = en[c];
-        double s[NP] = {0.0, 0.0, 0.0, 0.0};
-        for (int i0 = 0; i0 < e.n; i0 += NB) {
-            double ch[NB][NP], v[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int i = min(i0 + b, e.n - 1);   // a short batch re-reads its last row
-                const double *chp = a.chi + (int64_t)(e.row0 + i) * NP;
-#pragma unroll
-                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
-                v[b] = i0 + b < e.n ? pencil[e.zlo + i] : 0.0;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int l = 0; l < NP; ++l) s[l] += ch[b][l] * v[b];
-        }
-        int slot = e.slot;
-        merge_equal_slots<double, NP>(s, slot);
-        if (slot >= 0) {
-            double *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + slot) * NP;
-#pragma unroll
-            for (int l = 0; l < NP; ++l) atomicAdd(&pa[l], s[l]);
-        }
-    }
+// ---- atom-major projector block ----
+// The support rows of the box are listed atom by atom, in support-table order
+// (x-fastest columns, z contiguous, so consecutive entries are mostly
+// consecutive rows of chi): entry (row, off | slot << 16), off the element
+// offset of the point in the LDS box.  Every atom's run is padded to whole
+// chunks of 64 entries; a padding entry points at the zero pencil and has bit
+// 31 set.  The chunks of the box are split into one contiguous range per
+// wave, so a wave reads 64 consecutive entries per chunk (coalesced chi rows,
+// the same number of rows in every lane) where the column path has each lane
+// read its own pencil's rows, with run lengths that differ between lanes.
+constexpr int A64_CHUNK = 64;
+constexpr int A64_PAD = (int)0x80000000;
+template <int E>
+constexpr int64_t a64_list_cap() {
+    static_assert(A64_CHUNK == 64, "one chunk per wave");
+    return a64_list_cap_elems(E);
 }
 
-template <int NB>
-__device__ __forceinline__ void a64_col_update(const RegionArgs<double> &a,
-                                               const ColNL<double> &nl, double *pencil,
-                                               double half) {
-    ColEntry en[MAXC];
+// sum over the 64 lanes of the wave, the same in every lane: rotations
+// within each row of 16 lanes (DPP), then the four row sums
+__device__ __forceinline__ double a64_wave_sum(double x) {
+    x += dpp_f<0x128>(x);   // row_ror:8
+    x += dpp_f<0x124>(x);   // row_ror:4
+    x += dpp_f<0x122>(x);   // row_ror:2
+    x += dpp_f<0x121>(x);   // row_ror:1
+    auto lane_val = [&](int l) {
+        const long long b = __double_as_longlong(x);
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(b & 0xffffffffLL), l);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+        return __longlong_as_double(((long long)hi << 32) | lo);
+    };
+    return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
+}
+
+// in-box run of column (cx, cy) of atom slot sl: first row, LDS offset, length
+template <int ZS>
+__device__ __forceinline__ int a64_run(const RegionArgs<double> &a, const Slot &sl, int cx,
+                                       int cy, int dx, int dz, int &row, int &off) {
+    const int64_t ci = 2 * ((int64_t)sl.col + (int64_t)cy * sl.bx + cx);
+    const int r0 = a.colidx[ci], zc = a.colidx[ci + 1];
+    const int z0 = sl.oz + (zc & 0xffff);
+    const int zlo = max(z0, 0), zhi = min(z0 + (zc >> 16), dz);
+    row = r0 + (zlo - z0);
+    off = ((sl.oy + cy) * dx + (sl.ox + cx)) * ZS + zlo;
+    return max(zhi - zlo, 0);
+}
+
+// Builds the list for the nat atoms of the box into list (capacity
+// a64_list_cap entries) with per-atom row counts in acnt; returns the number
+// of chunks (block-uniform).  Atoms whose chunks would pass the capacity are
+// left out and status bit 2 is raised (the same condition as more than MAXC
+// supports crossing one pencil).
+template <int E, int ZS, int BLOCK>
+__device__ int a64_build_list(const RegionArgs<double> &a, const Slot *slots, int nat, int dx,
+                              int dy, int dz, int zero_off, int2 *list, int *acnt) {
+    constexpr int NW = BLOCK / 64;
+    constexpr int64_t CAP = a64_list_cap<E>();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto cols = [&](const Slot &sl, int &cx0, int &cy0, int &wx) {
+        cx0 = max(0, -sl.ox);
+        cy0 = max(0, -sl.oy);
+        wx = max(min(sl.bx, dx - sl.ox) - cx0, 0);
+        const int wy = max(min(sl.by, dy - sl.oy) - cy0, 0);
+        return wx * wy;
+    };
+    // pass 1: in-box rows per atom
+    for (int j = wave; j < nat; j += NW) {
+        const Slot sl = slots[j];
+        int cx0, cy0, wx;
+        const int ncols = cols(sl, cx0, cy0, wx);
+        int cnt = 0;
+        for (int q0 = 0; q0 < ncols; q0 += 64) {
+            const int q = q0 + lane;
+            int n = 0, row, off;
+            if (q < ncols) n = a64_run<ZS>(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, off);
+            cnt += wave_sum(n);
+        }
+        if (lane == 0) acnt[j] = cnt;
+    }
+    __syncthreads();
+    // chunk offsets: atoms in slot order, each padded to whole chunks
+    int nch = 0, fit = 0;
+    for (int j = 0; j < nat; ++j) {
+        nch += (acnt[j] + A64_CHUNK - 1) / A64_CHUNK;
+        if ((int64_t)nch * A64_CHUNK <= CAP) fit = nch;
+    }
+    if (fit < nch && threadIdx.x == 0) atomicOr(a.status, 2);
+    // pass 2: the entries
+    for (int j = wave; j < nat; j += NW) {
+        int base = 0;
+        for (int i = 0; i < j; ++i) base += (acnt[i] + A64_CHUNK - 1) / A64_CHUNK;
+        const int cnt = acnt[j], nj = (cnt + A64_CHUNK - 1) / A64_CHUNK;
+        if (base + nj > fit) continue;
+        int2 *out = list + (int64_t)base * A64_CHUNK;
+        const Slot sl = slots[j];
+        int cx0, cy0, wx;
+        const int ncols = cols(sl, cx0, cy0, wx);
+        int pos = 0;
+        for (int q0 = 0; q0 < ncols; q0 += 64) {
+            const int q = q0 + lane;
+            int n = 0, row = 0, off = 0;
+            if (q < ncols) n = a64_run<ZS>(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, off);
+            int inc = n;   // inclusive scan over the lanes
 #pragma unroll
-    for (int c = 0; c < MAXC; ++c) en[c] = c < nl.ncol ? nl.cols[c] : ColEntry{0, 0, 0, 0};
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
+            }
+            for (int i = 0; i < n; ++i)
+                out[pos + inc - n + i] = make_int2(row + i, (off + i) | (j << 16));
+            pos += __shfl(inc, 63, 64);
+        }
+        for (int e = cnt + lane; e < nj * A64_CHUNK; e += 64)
+            out[e] = make_int2(sl.start, zero_off | (j << 16) | A64_PAD);
+    }
+    return fit;
+}
+
+struct A64List {
+    const int2 *ent;
+    int g0, g1;   // this wave's chunks
+};
+
+// p_J += chi_J . v over the wave's chunks (v in the LDS box), summed per atom
+// in registers and added to pacc (the current parity) once per atom and wave
+template <int NCB>
+__device__ __forceinline__ void a64_am_dots(const RegionArgs<double> &a, const A64List &L,
+                                            const double *lds, double *pacc) {
+    const int lane = threadIdx.x & 63;
+    double s[NP] = {0.0, 0.0, 0.0, 0.0};
+    int cj = -1;
+    auto flush = [&]() {
+        double t[NP];
 #pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-        if (c >= nl.ncol) break;
-        const ColEntry e = en[c];
-        const double *pa = nl.pacc + ((int64_t)nl.par * nl.maxat + e.slot) * NP;
-        const double *sc = nl.scale + (int64_t)e.slot * NP;
-        double f[NP];
+        for (int l = 0; l < NP; ++l) t[l] = a64_wave_sum(s[l]);
+        if (lane == 0) {
 #pragma unroll
-        for (int l = 0; l < NP; ++l) f[l] = sc[l] * pa[l] * half;
-        for (int i0 = 0; i0 < e.n; i0 += NB) {
-            double ch[NB][NP];
+            for (int l = 0; l < NP; ++l) atomicAdd(&pacc[cj * NP + l], t[l]);
+        }
+    };
+    for (int g = L.g0; g < L.g1; g += NCB) {
+        int2 en[NCB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int i = min(i0 + b, e.n - 1);
-                const double *chp = a.chi + (int64_t)(e.row0 + i) * NP;
+        for (int b = 0; b < NCB; ++b)
+            en[b] = g + b < L.g1 ? L.ent[(int64_t)(g + b) * A64_CHUNK + lane] : make_int2(0, 0);
+        double ch[NCB][NP], v[NCB];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+            if (g + b < L.g1) {
+                const double *chp = a.chi + (int64_t)en[b].x * NP;
+#pragma unroll
+                for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
+                v[b] = lds[en[b].y & 0xffff];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+            if (g + b < L.g1) {
+                const int j = __builtin_amdgcn_readfirstlane((en[b].y >> 16) & 0x7fff);
+                if (j != cj) {
+                    if (cj >= 0) flush();
+                    cj = j;
+#pragma unroll
+                    for (int l = 0; l < NP; ++l) s[l] = 0.0;
+                }
+#pragma unroll
+                for (int l = 0; l < NP; ++l) s[l] = fma(ch[b][l], v[b], s[l]);
+            }
+        }
+    }
+    if (cj >= 0) flush();
+}
+
+// v(x) += sum_l chi_Jl(x) f_Jl, f_Jl = half * scale_Jl * p_Jl, over the wave's
+// chunks, with LDS atomics (supports of several atoms overlap)
+template <int NCB>
+__device__ __forceinline__ void a64_am_update(const RegionArgs<double> &a, const A64List &L,
+                                              double *lds, const double *pacc,
+                                              const double *scale, double half) {
+    const int lane = threadIdx.x & 63;
+    double f[NP] = {0.0, 0.0, 0.0, 0.0};
+    int cj = -1;
+    for (int g = L.g0; g < L.g1; g += NCB) {
+        int2 en[NCB];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+            en[b] = g + b < L.g1 ? L.ent[(int64_t)(g + b) * A64_CHUNK + lane] : make_int2(0, 0);
+        double ch[NCB][NP];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+            if (g + b < L.g1) {
+                const double *chp = a.chi + (int64_t)en[b].x * NP;
 #pragma unroll
                 for (int l = 0; l < NP; ++l) ch[b][l] = chp[l];
             }
-            __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (i0 + b < e.n)
-                    pencil[e.zlo + i0 + b] +=
-                        ch[b][0] * f[0] + ch[b][1] * f[1] + ch[b][2] * f[2] + ch[b][3] * f[3];
+        for (int b = 0; b < NCB; ++b) {
+            if (g + b < L.g1) {
+                const int j = __builtin_amdgcn_readfirstlane((en[b].y >> 16) & 0x7fff);
+                if (j != cj) {
+                    cj = j;
+#pragma unroll
+                    for (int l = 0; l < NP; ++l) f[l] = scale[j * NP + l] * pacc[j * NP + l] * half;
+                }
+                const double u = ch[b][0] * f[0] + ch[b][1] * f[1] + ch[b][2] * f[2] + ch[b][3] * f[3];
+                if (en[b].y >= 0) atomicAdd(&lds[en[b].y & 0xffff], u);
+            }
         }
     }
 }
@@ -310,7 +457,10 @@ __device__ __forceinline__ void a64_col_update(const RegionArgs<double> &a,
 // and each next one before the diagonal term of the current batch.  The
 // result goes to slot row out (element offset; svo is the lane's byte offset
 // in a row, dvo its byte offset in a plane of D); the projections chi . cur are
-// left in parity buffer nl.par ^ 1.
+// left in parity buffer nl.par ^ 1.  With atoms in the box the rank-4 term is
+// added between two more barriers: the new vector goes to the own pencil, the
+// waves add their chunks' terms to the box with LDS atomics, and the thread
+// reads its pencil back.
 template <int E, int R, int ZS, int BLOCK>
 __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
                                          const StepCtx<double, E, R> &c,
@@ -318,7 +468,8 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
                                          uint32_t plane, int gz0, int n2, double (&cur)[E],
                                          double (&nw)[E], double *lds, ColNL<double> &nl,
                                          bool first, __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
-                                         uint32_t out, int inj_z, double inj, int ncw) {
+                                         uint32_t out, int inj_z, double inj,
+                                         const A64List &L) {
     constexpr int EE = E * E;
     constexpr int DB = A64_DB;
     constexpr int NDB = (E + DB - 1) / DB;
@@ -342,7 +493,7 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
         }
     }
     __syncthreads();
-    if (c.nat) a64_col_dots<A64_NB>(a, nl, ncw, c.mine);
+    if (c.nat) a64_am_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
     if (c.active) {
         // an opaque zero keeps the plane offsets from being hoisted out of the
         // step loop
@@ -404,7 +555,12 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
     }
     if (c.nat) {
         if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
-        if (nl.ncol) a64_col_update<A64_NB>(a, nl, c.mine, first ? 0.5 : 1.0);
+        // every pencil holds the new vector (and every v_k has been read back)
+        // before the atomics of other waves touch it
+        __syncthreads();
+        a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP, nl.scale,
+                               first ? 0.5 : 1.0);
+        __syncthreads();
         if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
         col_zero_next<double, BLOCK, false>(nl, c.nat);
     }
@@ -421,6 +577,20 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
 #pragma unroll
         for (int z = 0; z < E; ++z) a64_st(Sr, svo, (out + (uint32_t)(z * EE)) * 8u, cur[z]);
     }
+}
+
+// projections of one vector without a recurrence step (atom-major block)
+template <int E, int R, int ZS, int BLOCK>
+__device__ __forceinline__ void a64_dots_only(const RegionArgs<double> &a,
+                                              const StepCtx<double, E, R> &c,
+                                              const double (&vec)[E], ColNL<double> &nl,
+                                              const A64List &L, double *lds) {
+    if (c.active) store_pencil<double, E, ZS>(c.mine, vec);
+    __syncthreads();
+    if (c.nat) a64_am_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
+    __syncthreads();
+    col_zero_next<double, BLOCK, false>(nl, c.nat);
+    nl.par ^= 1;
 }
 
 template <int E, int R>
@@ -461,6 +631,9 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
     T *Qrow = Prow + a64_proj_elems(K);      // q_k = chi . vt_{k+1}   [k][atom][NP]
     Slot *slots = reinterpret_cast<Slot *>(Qrow + a64_proj_elems(K));
     ColEntry *colbuf = reinterpret_cast<ColEntry *>(slots + AT);
+    int2 *alist = reinterpret_cast<int2 *>(colbuf + BLOCK * MAXC);
+    int *acnt = reinterpret_cast<int *>(alist + a64_list_cap<E>());
+    static_assert((int64_t)(E * E + 1) * ZS < 65536, "box offsets fit 16 bits");
 
     for (;;) {
         if (tid == 0) {
@@ -520,10 +693,18 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         ColNL<T> nl{};
         nl.cols = mycols;
         nl.ncol = ncol;
-        const int ncw = a64_wave_max(ncol);   // every lane runs the wave's count (DPP merge)
+        const int ncw = a64_wave_max(ncol);   // passes of the final pass's column loop
         nl.pacc = &pacc[0][0][0];
         nl.scale = &pfac[0][0];
         nl.maxat = AT;
+        A64List L{alist, 0, 0};
+        if (c.nat) {
+            const int nch = a64_build_list<E, ZS, BLOCK>(a, slots, c.nat, c.dx, c.dy, c.dz,
+                                                        npen * ZS, alist, acnt);
+            const int w = tid >> 6;
+            L.g0 = w * nch / (BLOCK / 64);
+            L.g1 = (w + 1) * nch / (BLOCK / 64);
+        }
         __syncthreads();
 
         // ---- forward sweep: v_0 .. v_{K-1} and p_k = chi . v_k to the slot ----
@@ -539,11 +720,11 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
             for (int z = 0; z < E; ++z) a64_st(Sr, svo, (VO + (uint32_t)(z * EE)) * 8u, X[z]);
         for (int k = 0; k + 1 <= K - 1; ++k) {
             a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, k == 0,
-                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0, ncw);
+                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0, L);
             a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)k * AT * NP);
         }
         // X = v_{K-1}: its projections without a step
-        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, X, nl);
+        a64_dots_only<E, R, ZS, BLOCK>(a, c, X, nl, L, lds);
         a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)(K - 1) * AT * NP);
 
         // ---- reverse sweep: vt_{k+1} and q_k = chi . vt_{k+1} to the slot ----
@@ -561,11 +742,11 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         for (int k = K - 1; k >= 1; --k) {
             const T ak = 2.0 * (gr * aa.coef_c[k] + gu * aa.coef_d[k]);
             a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, false,
-                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak, ncw);
+                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak, L);
             a64_store_proj<BLOCK>(nl, c.nat, Qrow + (int64_t)k * AT * NP);
         }
         // X = vt_1: its projections q_0 without a step
-        col_dots_only<T, E, R, ZS, BLOCK, false>(a, c, X, nl);
+        a64_dots_only<E, R, ZS, BLOCK>(a, c, X, nl, L, lds);
         a64_store_proj<BLOCK>(nl, c.nat, Qrow);
         __syncthreads();   // the slot's projection rows are read by other threads below
 
