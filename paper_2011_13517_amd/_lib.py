@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsq.so")
+# SQ_LIB names a variant build of the same library (build.py --name) for A/B
+# measurements; it must exist like the default one
+LIB_PATH = os.environ.get("SQ_LIB") or os.path.join(HERE, "libsq.so")
 
 SQ_OK, SQ_ERR_ARG, SQ_ERR_HIP, SQ_ERR_OOM = 0, -1, -2, -3
 SQ_ERR_NOT_CONVERGED, SQ_ERR_SPECTRUM, SQ_ERR_STATE = -4, -5, -6

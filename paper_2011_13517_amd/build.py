@@ -3,6 +3,11 @@
 Every HIP source under csrc/ is compiled to an object in _build/ (in
 parallel) and linked into paper_2011_13517_amd/libsq.so.  Packed-FP32
 instructions are disabled for all device code.
+
+A variant build for A/B measurements (``python -m paper_2011_13517_amd.build
+--define A64_MFMA_DOTS=1 --name mfma``) compiles with extra macro definitions
+into _build_<name>/ and links libsq_<name>.so beside the default library;
+the Python binding loads it when SQ_LIB names it.
 """
 from __future__ import annotations
 
@@ -27,31 +32,43 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+def _compile(src, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC] + FLAGS + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, defines=(), name: str = "") -> str:
+    build_dir = BUILD + (f"_{name}" if name else "")
+    lib = LIB[:-3] + f"_{name}.so" if name else LIB
+    extra = ["-D" + d for d in defines]
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + f".tmp{os.getpid()}"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, extra), srcs))
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
-    return LIB
+        print(f"built {lib}", file=sys.stderr)
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    import argparse
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--define", action="append", default=[], metavar="NAME=VALUE",
+                    help="extra macro definition (variant builds)")
+    ap.add_argument("--name", default="", help="variant name: libsq_<name>.so")
+    args = ap.parse_args()
+    if args.define and not args.name:
+        ap.error("a build with --define needs --name (the default library stays as built)")
+    build(defines=args.define, name=args.name)

@@ -67,6 +67,9 @@ constexpr int A64_DB = 9;          // planes of the diagonal per load batch
 #ifndef A64_XY_SPLIT
 #define A64_XY_SPLIT 3             // x/y pipeline units per pencil (0: plain loop)
 #endif
+#ifndef A64_MFMA_DOTS
+#define A64_MFMA_DOTS 0            // projections with FP64 matrix instructions (1) or VALU (0)
+#endif
 #ifndef A64_NCB
 #define A64_NCB 2                  // chunks per load batch of the atom-major block
 #endif
@@ -405,6 +408,83 @@ __device__ __forceinline__ void a64_am_dots(const RegionArgs<double> &a, const A
     if (cj >= 0) flush();
 }
 
+// Projections with FP64 matrix instructions (v_mfma_f64_4x4x4f64: four
+// independent 4x4x4 blocks per wave; lane 16k + 4b + i holds A[b][i][k] and
+// B[b][k][i], lane 16i + 4b + j holds D[b][i][j]).  Per chunk, four
+// instructions take 16 rows each: in block b, A[i][k] = chi_i of row
+// 16t + 4b + k and B[k][0] = v of that row (the other three columns of B are
+// zero), so D[i][0] of the four blocks accumulates the atom's projections.
+// A compile-time alternative to the VALU routine above (A64_MFMA_DOTS), kept
+// for the measured comparison: one useful column in four, and four entry,
+// chi and LDS loads per lane and chunk instead of one.
+template <int NCB>
+__device__ __forceinline__ void a64_am_dots_mfma(const RegionArgs<double> &a, const A64List &L,
+                                                 const double *lds, double *pacc) {
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    int cj = -1;
+    auto flush = [&]() {
+        // D[i][0] of block b is in lane 16 i + 4 b
+        auto at = [&](int l) {
+            const long long bb = __double_as_longlong(acc);
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(bb & 0xffffffffLL), l);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(bb >> 32), l);
+            return __longlong_as_double(((long long)hi << 32) | lo);
+        };
+        double t[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            t[i] = (at(16 * i) + at(16 * i + 4)) + (at(16 * i + 8) + at(16 * i + 12));
+        if (lane == 0) {
+#pragma unroll
+            for (int l = 0; l < NP; ++l) atomicAdd(&pacc[cj * NP + l], t[l]);
+        }
+    };
+    for (int g = L.g0; g < L.g1; g += NCB) {
+        int2 en[NCB][4];
+        double av[NCB][4], bv[NCB][4];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                en[b][t] = g + b < L.g1
+                               ? L.ent[(int64_t)(g + b) * A64_CHUNK + 16 * t +
+                                       4 * ((lane >> 2) & 3) + (lane >> 4)]
+                               : make_int2(0, 0);
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                av[b][t] = a.chi[(int64_t)en[b][t].x * NP + (lane & 3)];
+                const double v = lds[en[b][t].y & 0xffff];
+                bv[b][t] = (lane & 3) == 0 ? v : 0.0;
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+            if (g + b < L.g1) {
+                const int j = __builtin_amdgcn_readfirstlane((en[b][0].y >> 16) & 0x7fff);
+                if (j != cj) {
+                    if (cj >= 0) flush();
+                    cj = j;
+                    acc = 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = __builtin_amdgcn_mfma_f64_4x4x4f64(av[b][t], bv[b][t], acc, 0, 0, 0);
+            }
+        }
+    }
+    if (cj >= 0) flush();
+}
+
+template <int NCB>
+__device__ __forceinline__ void a64_dots(const RegionArgs<double> &a, const A64List &L,
+                                         const double *lds, double *pacc) {
+    if constexpr (A64_MFMA_DOTS) a64_am_dots_mfma<NCB>(a, L, lds, pacc);
+    else a64_am_dots<NCB>(a, L, lds, pacc);
+}
+
 // v(x) += sum_l chi_Jl(x) f_Jl, f_Jl = half * scale_Jl * p_Jl, over the wave's
 // chunks, with LDS atomics (supports of several atoms overlap)
 template <int NCB>
@@ -493,7 +573,7 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
         }
     }
     __syncthreads();
-    if (c.nat) a64_am_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
+    if (c.nat) a64_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
     if (c.active) {
         // an opaque zero keeps the plane offsets from being hoisted out of the
         // step loop
@@ -587,7 +667,7 @@ __device__ __forceinline__ void a64_dots_only(const RegionArgs<double> &a,
                                               const A64List &L, double *lds) {
     if (c.active) store_pencil<double, E, ZS>(c.mine, vec);
     __syncthreads();
-    if (c.nat) a64_am_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
+    if (c.nat) a64_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
     __syncthreads();
     col_zero_next<double, BLOCK, false>(nl, c.nat);
     nl.par ^= 1;
