@@ -527,34 +527,46 @@ __device__ __forceinline__ void a64_am_update(const RegionArgs<double> &a, const
 
 // One recurrence step with the two live vectors in registers:
 //   v_{k+1} = scale (2 Hs v_k - v_{k-1})  (+ inj at plane inj_z of the owning
-// thread), scale = 1/2 on the first step.  On entry cur = v_k and nw = v_{k-1};
-// on exit cur = v_{k+1} and nw = v_k.  The new vector is formed in place in nw
-// and moved to cur after the second barrier.  cur is published to the LDS box (its
-// registers are free after the z neighbours, which are taken from them before
-// the first barrier, and it is re-read from the thread's own pencil after the
-// second barrier).  The diagonal D of the pencil is loaded in batches of
-// A64_DB planes, the first before the x/y neighbours (whose LDS work hides it)
-// and each next one before the diagonal term of the current batch.  The
-// result goes to slot row out (element offset; svo is the lane's byte offset
-// in a row, dvo its byte offset in a plane of D); the projections chi . cur are
-// left in parity buffer nl.par ^ 1.  With atoms in the box the rank-4 term is
-// added between two more barriers: the new vector goes to the own pencil, the
-// waves add their chunks' terms to the box with LDS atomics, and the thread
-// reads its pencil back.
+// thread), scale = 1/2 on the first step.  The rank-4 projector term of each
+// new vector is deferred into the next step: on entry cur holds v_k without
+// it (pend = the halving factor it takes, 0 when there is none) and nw holds
+// v_{k-1}.  cur is published to the LDS box; with atoms in the box the waves
+// add the deferred term to the box with LDS atomics (chunks of the row list,
+// projections of the previous step in parity buffer nl.par ^ 1) and the
+// thread reads its completed pencil back, which goes to slot row in_row
+// (element offset; svo is the lane's byte offset in a row, dvo its byte
+// offset in a plane of D).  The z neighbours come from the registers of cur
+// (its last use in the step); the projections chi . v_k go to parity buffer
+// nl.par; the x/y neighbours and the diagonal come from the box, D in batches
+// of A64_DB planes, the first before the x/y part (whose LDS work hides it)
+// and each next one before the diagonal term of the current batch.  The new
+// vector is formed in place in nw and, after the last barrier, moved to cur,
+// and nw re-reads v_k from the own pencil.  Three barriers per step with
+// atoms in the box (the term added at the end of its own step would take two
+// more barriers and a store and read-back of the own pencil).
 template <int E, int R, int ZS, int BLOCK>
-__device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
-                                         const StepCtx<double, E, R> &c,
-                                         __amdgpu_buffer_rsrc_t Dr, uint32_t dvo,
-                                         uint32_t plane, int gz0, int n2, double (&cur)[E],
-                                         double (&nw)[E], double *lds, ColNL<double> &nl,
-                                         bool first, __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
-                                         uint32_t out, int inj_z, double inj,
-                                         const A64List &L) {
+__device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
+                                           const StepCtx<double, E, R> &c,
+                                           __amdgpu_buffer_rsrc_t Dr, uint32_t dvo,
+                                           uint32_t plane, int gz0, int n2, double (&cur)[E],
+                                           double (&nw)[E], double *lds, ColNL<double> &nl,
+                                           bool first, __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
+                                           uint32_t in_row, int inj_z, double inj,
+                                           const A64List &L, double pend) {
     constexpr int EE = E * E;
     constexpr int DB = A64_DB;
     constexpr int NDB = (E + DB - 1) / DB;
+    if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
+    __syncthreads();
+    if (c.nat && pend != 0.0) {
+        a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP,
+                               nl.scale, pend);
+        __syncthreads();
+        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
+    }
     if (c.active) {
-        store_pencil<double, E, ZS>(c.mine, cur);
+#pragma unroll
+        for (int z = 0; z < E; ++z) a64_st(Sr, svo, (in_row + (uint32_t)(z * EE)) * 8u, cur[z]);
         // z neighbours from the registers of cur (its last use in the step):
         // nw <- sum_p cz_p (cur[z + p] + cur[z - p]) - nw
 #pragma unroll
@@ -572,11 +584,8 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
             nw[z] = r;
         }
     }
-    __syncthreads();
     if (c.nat) a64_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
     if (c.active) {
-        // an opaque zero keeps the plane offsets from being hoisted out of the
-        // step loop
         int salt = 0;
         asm volatile("" : "+s"(salt));
         const int zmax = c.dz - 1 + salt;
@@ -593,12 +602,9 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
             }
         };
         load_d(0);
-        // phase order is kept as written: a diagonal batch hoisted into the
-        // x/y part only adds live registers there
         __builtin_amdgcn_sched_barrier(0);
         a64_xy<E, R, ZS>(nw, c, lds);
         __builtin_amdgcn_sched_barrier(0);
-        // diagonal: D times the own pencil, read back from the LDS box
         int s3 = 0;
         asm volatile("" : "+v"(s3));
         const double *mw = c.mine + s3;
@@ -614,7 +620,6 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
         }
     }
     __syncthreads();
-    // roles for the next step: cur <- the new vector, nw <- v_k (own pencil)
 #pragma unroll
     for (int z = 0; z < E; ++z) cur[z] = nw[z];
     if (c.active) load_pencil<double, E, ZS>(c.mine, nw);
@@ -622,8 +627,6 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
 #pragma unroll
         for (int z = 0; z < E; ++z) cur[z] *= 0.5;
     }
-    // planes past a z-clipped box edge: recomputed per step from an opaque
-    // copy of dz (hoisted, the E plane masks would pin 2E scalar registers)
     {
         int salt = 0;
         asm volatile("" : "+s"(salt));
@@ -633,40 +636,37 @@ __device__ __forceinline__ void a64_step(const RegionArgs<double> &a,
             for (int z = 0; z < E; ++z) cur[z] = (z < dz) ? cur[z] : 0.0;
         }
     }
-    if (c.nat) {
-        if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
-        // every pencil holds the new vector (and every v_k has been read back)
-        // before the atomics of other waves touch it
-        __syncthreads();
-        a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP, nl.scale,
-                               first ? 0.5 : 1.0);
-        __syncthreads();
-        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
-        col_zero_next<double, BLOCK, false>(nl, c.nat);
-    }
+    if (c.nat) col_zero_next<double, BLOCK, false>(nl, c.nat);
     nl.par ^= 1;
-    // the node's own lane only; its plane compares are redone per step (an
-    // opaque copy of inj_z) instead of E masks held across the loop
     if (inj_z >= 0) {
         int iz = inj_z;
         asm volatile("" : "+v"(iz));
 #pragma unroll
         for (int z = 0; z < E; ++z) cur[z] += (z == iz) ? inj : 0.0;
     }
-    if (c.active) {
-#pragma unroll
-        for (int z = 0; z < E; ++z) a64_st(Sr, svo, (out + (uint32_t)(z * EE)) * 8u, cur[z]);
-    }
 }
 
-// projections of one vector without a recurrence step (atom-major block)
+// the last vector of a sweep: its deferred rank-4 term, its slot row and its
+// projections chi . v (to parity buffer nl.par, then flipped), without a step
 template <int E, int R, int ZS, int BLOCK>
-__device__ __forceinline__ void a64_dots_only(const RegionArgs<double> &a,
-                                              const StepCtx<double, E, R> &c,
-                                              const double (&vec)[E], ColNL<double> &nl,
-                                              const A64List &L, double *lds) {
-    if (c.active) store_pencil<double, E, ZS>(c.mine, vec);
+__device__ __forceinline__ void a64_finish_d(const RegionArgs<double> &a,
+                                             const StepCtx<double, E, R> &c, double (&cur)[E],
+                                             ColNL<double> &nl, const A64List &L, double *lds,
+                                             __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
+                                             uint32_t in_row, double pend) {
+    constexpr int EE = E * E;
+    if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
     __syncthreads();
+    if (c.nat && pend != 0.0) {
+        a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP,
+                               nl.scale, pend);
+        __syncthreads();
+        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
+    }
+    if (c.active) {
+#pragma unroll
+        for (int z = 0; z < E; ++z) a64_st(Sr, svo, (in_row + (uint32_t)(z * EE)) * 8u, cur[z]);
+    }
     if (c.nat) a64_dots<A64_NCB>(a, L, lds, nl.pacc + (int64_t)nl.par * nl.maxat * NP);
     __syncthreads();
     col_zero_next<double, BLOCK, false>(nl, c.nat);
@@ -796,15 +796,17 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
             X[z] = (is_ctr && z == cz0) ? 1.0 : 0.0;
             Y[z] = 0.0;
         }
-        if (c.active)
-            for (int z = 0; z < E; ++z) a64_st(Sr, svo, (VO + (uint32_t)(z * EE)) * 8u, X[z]);
+        // step k stores v_k; the rank-4 term of v_{k+1} (halved after the
+        // first step) is added at the start of step k + 1
         for (int k = 0; k + 1 <= K - 1; ++k) {
-            a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, k == 0,
-                                      Sr, svo, VO + (uint32_t)((k + 1) * E3), -1, 0.0, L);
+            const double pend = k == 0 ? 0.0 : (k == 1 ? 0.5 : 1.0);
+            a64_step_d<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, k == 0,
+                                        Sr, svo, VO + (uint32_t)(k * E3), -1, 0.0, L, pend);
             a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)k * AT * NP);
         }
-        // X = v_{K-1}: its projections without a step
-        a64_dots_only<E, R, ZS, BLOCK>(a, c, X, nl, L, lds);
+        a64_finish_d<E, R, ZS, BLOCK>(a, c, X, nl, L, lds, Sr, svo,
+                                      VO + (uint32_t)((K - 1) * E3),
+                                      K == 1 ? 0.0 : (K == 2 ? 0.5 : 1.0));
         a64_store_proj<BLOCK>(nl, c.nat, Prow + (int64_t)(K - 1) * AT * NP);
 
         // ---- reverse sweep: vt_{k+1} and q_k = chi . vt_{k+1} to the slot ----
@@ -815,18 +817,16 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
             X[z] = (is_ctr && z == cz0) ? aK : 0.0;   // vt_K
             Y[z] = 0.0;
         }
-        if (c.active)
-            for (int z = 0; z < E; ++z)
-                a64_st(Sr, svo, (TO + (uint32_t)((K - 1) * E3 + z * EE)) * 8u, X[z]);
         const int iz = is_ctr ? cz0 : -1;
+        // step k stores vt_{k+1}
         for (int k = K - 1; k >= 1; --k) {
             const T ak = 2.0 * (gr * aa.coef_c[k] + gu * aa.coef_d[k]);
-            a64_step<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, false,
-                                      Sr, svo, TO + (uint32_t)((k - 1) * E3), iz, ak, L);
+            a64_step_d<E, R, ZS, BLOCK>(a, c, Dr, dvo, pl, gz0, n2, X, Y, lds, nl, false,
+                                        Sr, svo, TO + (uint32_t)(k * E3), iz, ak, L,
+                                        k == K - 1 ? 0.0 : 1.0);
             a64_store_proj<BLOCK>(nl, c.nat, Qrow + (int64_t)k * AT * NP);
         }
-        // X = vt_1: its projections q_0 without a step
-        a64_dots_only<E, R, ZS, BLOCK>(a, c, X, nl, L, lds);
+        a64_finish_d<E, R, ZS, BLOCK>(a, c, X, nl, L, lds, Sr, svo, TO, K >= 2 ? 1.0 : 0.0);
         a64_store_proj<BLOCK>(nl, c.nat, Qrow);
         __syncthreads();   // the slot's projection rows are read by other threads below
 
