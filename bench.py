@@ -574,6 +574,9 @@ def main():
                     help="skip the oracle comparisons of the main workload (they launch the "
                          "timed kernels again on small node subsets; profiling runs use this so "
                          "that per-kernel averages are those of the timed launches)")
+    ap.add_argument("--local-only", action="store_true",
+                    help="the workload without its atoms (local Hamiltonian only): a profiling "
+                         "aid that times the stencil and diagonal apart from the projector block")
     ap.add_argument("--c5-adjoint-stride", type=int, default=8)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -602,6 +605,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     prob = synth.config(args.config)
+    if args.local_only:
+        prob = synth.without_projectors(prob)
     log(f"workload {prob.name}: {prob.n_nodes} nodes, K={prob.order}, atoms={prob.n_atoms}")
     # FP32 forward; FP64 adjoint keeping every v_k of its in-flight regions
     ctx = sq.Context(prob, precision=1, adjoint_precision=0, ckpt_every=1)

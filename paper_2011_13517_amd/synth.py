@@ -313,6 +313,14 @@ def config(c: int) -> Problem:
     raise ValueError(f"unknown config {c}")
 
 
+def without_projectors(prob: Problem) -> Problem:
+    """The same grid, potential, nodes and regions with no nonlocal term: the
+    local part of the Hamiltonian alone (used to time the stencil and diagonal
+    apart from the projector block)."""
+    return dataclasses.replace(prob, name=prob.name + "_local", n_atoms=0, sup_off=None,
+                               sup_idx=None, chi=None, dchi=None, c=None, atom_pos=None)
+
+
 # lambda_f used by the uneven-region workload, which has no electron count of its
 # own: the FP64 Fermi level of the 64^3 workload (config 2), computed by the oracle
 # alone over all of its nodes (tests/golden/make_c2_lambda_f.py -> c2_lambda_f.txt)
