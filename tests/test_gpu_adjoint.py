@@ -228,3 +228,21 @@ def test_fp64_adjoint_edge27_clipped_boxes(order):
     assert rel(dV, gV) < 1e-10 and rel(dRg, dR) < 1e-10
     dV2, none = gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 0, nodes=nodes, with_dR=False)
     assert none is None and rel(dV2, gV) < 1e-10
+
+
+def test_fp64_adjoint_edge27_too_many_atoms_reports_error():
+    """A 27^3 FP64 region whose box meets more atoms than the edge-27 kernel's atom
+    table holds (48): the adjoint must report SQ_ERR_ARG through the status word,
+    not return a truncated gradient.  60 small supports (r_c = 0.6 bohr) packed in
+    a 15-bohr cell keep every pencil below the column-entry limit, so the atom table
+    is the only limit hit; the FP32 forward (128-atom table) runs as usual."""
+    print("[case] FP64 adjoint edge27 with 60 atoms in one box", flush=True)
+    prob = synth.small_problem(91, n=(30, 30, 30), h=(0.5, 0.5, 0.5), bc=synth.BC_PERIODIC,
+                               rcut=(13, 13, 13), n_atoms=60, rc=0.6, order=4, kT=0.2,
+                               fd_order=4)
+    lmin, lmax = O.gershgorin(prob)
+    lf = 0.5 * (lmin + lmax)
+    nodes = np.array([0, 4321, 13000], dtype=np.int64)
+    g_rho, g_u = _cotangents(nodes.size, 3)
+    with pytest.raises(RuntimeError, match="more atoms"):
+        gpu_adjoint(prob, lmin, lmax, lf, g_rho, g_u, 1, nodes=nodes, adjoint_precision=0)
