@@ -42,6 +42,11 @@ def _compile(src, build_dir=BUILD, extra=()):
 
 
 def build(verbose: bool = True, defines=(), name: str = "") -> str:
+    if name and not name.replace("_", "").isalnum():
+        raise ValueError(f"variant name {name!r}: letters, digits and '_' only")
+    for d in defines:
+        if not d.split("=", 1)[0].replace("_", "").isalnum():
+            raise ValueError(f"macro definition {d!r}: NAME or NAME=VALUE")
     build_dir = BUILD + (f"_{name}" if name else "")
     lib = LIB[:-3] + f"_{name}.so" if name else LIB
     extra = ["-D" + d for d in defines]
