@@ -533,9 +533,12 @@ __device__ __forceinline__ void a64_am_update(const RegionArgs<double> &a, const
 // v_{k-1}.  cur is published to the LDS box; with atoms in the box the waves
 // add the deferred term to the box with LDS atomics (chunks of the row list,
 // projections of the previous step in parity buffer nl.par ^ 1) and the
-// thread reads its completed pencil back, which goes to slot row in_row
-// (element offset; svo is the lane's byte offset in a row, dvo its byte
-// offset in a plane of D).  The z neighbours come from the registers of cur
+// thread reads its completed pencil back.  The completed v_k goes to slot row
+// in_row (element offset; svo is the lane's byte offset in a row, dvo its
+// byte offset in a plane of D) from the diagonal term's reads of the own
+// pencil, batch by batch: loads and stores share one memory counter, so
+// stores issued before the step's loads would have to drain before those
+// loads could be used.  The z neighbours come from the registers of cur
 // (its last use in the step); the projections chi . v_k go to parity buffer
 // nl.par; the x/y neighbours and the diagonal come from the box, D in batches
 // of A64_DB planes, the first before the x/y part (whose LDS work hides it)
@@ -565,8 +568,6 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
         if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
     }
     if (c.active) {
-#pragma unroll
-        for (int z = 0; z < E; ++z) a64_st(Sr, svo, (in_row + (uint32_t)(z * EE)) * 8u, cur[z]);
         // z neighbours from the registers of cur (its last use in the step):
         // nw <- sum_p cz_p (cur[z + p] + cur[z - p]) - nw
 #pragma unroll
@@ -614,7 +615,14 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
 #pragma unroll
             for (int i = 0; i < DB; ++i) {
                 const int z = b * DB + i;
-                if (z < E) nw[z] = fma(d[b][i], mw[z], nw[z]);
+                if (z < E) {
+                    // the completed v_k to its slot row, from the own-pencil value the
+                    // diagonal term reads anyway: issued here, after the batch's loads,
+                    // the stores stay in flight while the next batch is waited for
+                    const double vz = mw[z];
+                    nw[z] = fma(d[b][i], vz, nw[z]);
+                    a64_st(Sr, svo, (in_row + (uint32_t)(z * EE)) * 8u, vz);
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
