@@ -15,7 +15,9 @@
 // 160 KB):
 //  * Thread t owns the z-pencil (t mod dx, t / dx) of the two live vectors in
 //    VGPRs; the LDS holds the box once (x/y neighbours) plus one zero pencil,
-//    and the per-atom projections.
+//    and the per-atom projections.  The box keeps planes 0 .. E-2 of every
+//    pencil at an even stride (16-byte reads and writes of plane pairs) and
+//    plane E-1 of all pencils in a block of its own.
 //  * Projector block atom-major: at region start the box's support rows are
 //    listed atom by atom in chunks of 64 (row, LDS offset) entries; in every
 //    step each wave walks its share of the chunks, forming chi . v with wave
@@ -65,7 +67,7 @@ constexpr int A64_DB = 9;          // planes of the diagonal per load batch
 #define A64_FZB 3                  // planes per batch of the final dV / dR pass
 #endif
 #ifndef A64_XY_SPLIT
-#define A64_XY_SPLIT 3             // x/y pipeline units per pencil (0: plain loop)
+#define A64_XY_SPLIT 3             // x/y pipeline units per pencil
 #endif
 #ifndef A64_MFMA_DOTS
 #define A64_MFMA_DOTS 0            // projections with FP64 matrix instructions (1) or VALU (0)
@@ -152,6 +154,54 @@ struct A64Lane {
     int tid, px, py;
 };
 
+// LDS box of this kernel: planes 0 .. E-2 of pencil n at n (E - 1), an even
+// stride, so every pencil starts 16-byte aligned and pairs of planes move as
+// 16-byte reads and writes; plane E - 1 of every pencil after them, at
+// a64_xb + n.  The same size as pencils of E planes; with odd E-plane pencils
+// half of them start 8 bytes off and the reads go as 8-byte pairs, which an
+// LDS read probe of this pattern measured at 112 B/clk/CU against 157.
+template <int E>
+constexpr int a64_xb() {
+    static_assert(E % 2 == 1, "an even stride E - 1");
+    return (E * E + 1) * (E - 1);
+}
+template <int E>
+__device__ __forceinline__ int a64_off(int n, int z) {
+    return z < E - 1 ? n * (E - 1) + z : a64_xb<E>() + n;
+}
+// planes Z0 .. Z0 + H - 1 (those below E) of pencil n to q[0 .. H-1]
+template <int E, int Z0, int H, typename Q>
+__device__ __forceinline__ void a64_box_get(Q &q, const double *lds, int n) {
+    constexpr int PS = E - 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const int z = Z0 + i;
+        if (z >= E) continue;
+        const bool pair = (z % 2 == 0) && z + 1 < PS && i + 1 < H;
+        const bool second = (z % 2 == 1) && i > 0 && z < PS;
+        if (pair) {
+            const double2 d = *reinterpret_cast<const double2 *>(lds + n * PS + z);
+            q[i] = d.x;
+            q[i + 1] = d.y;
+        } else if (!second) {
+            q[i] = z < PS ? lds[n * PS + z] : lds[a64_xb<E>() + n];
+        }
+    }
+}
+// all E planes of v to pencil n
+template <int E>
+__device__ __forceinline__ void a64_box_put(double *lds, int n, const double (&v)[E]) {
+    constexpr int PS = E - 1;
+#pragma unroll
+    for (int z = 0; z < PS; z += 2) {
+        double2 d;
+        d.x = v[z];
+        d.y = v[z + 1];
+        *reinterpret_cast<double2 *>(lds + n * PS + z) = d;
+    }
+    lds[a64_xb<E>() + n] = v[E - 1];
+}
+
 template <int E, int R, int ZS, int NS, int U>
 __device__ __forceinline__ void a64_xy_load(double (&q)[(E + NS - 1) / NS],
                                             const StepCtx<double, E, R> &c, const A64Lane &l,
@@ -163,12 +213,7 @@ __device__ __forceinline__ void a64_xy_load(double (&q)[(E + NS - 1) / NS],
     else if constexpr (dir == 1) n = (l.px - p >= 0) ? l.tid - p : c.npen;
     else if constexpr (dir == 2) n = (l.py + p < c.dy) ? l.tid + p * c.dx : c.npen;
     else n = (l.py - p >= 0) ? l.tid - p * c.dx : c.npen;
-    // 8-byte reads (pencils start at odd multiples of 8 bytes when ZS is odd);
-    // the compiler pairs them into two-address LDS reads
-    const double *b = lds + n * ZS + z0;
-#pragma unroll
-    for (int i = 0; i < HZ; ++i)
-        if (z0 + i < E) q[i] = b[i];
+    a64_box_get<E, z0, HZ>(q, lds, n);
 }
 
 template <int E, int R, int ZS, int NS, int U>
@@ -210,21 +255,8 @@ __device__ __forceinline__ void a64_xy(double (&acc)[E], const StepCtx<double, E
     int s2 = 0;
     asm volatile("" : "+v"(s2));
     const A64Lane l{(int)threadIdx.x + s2, c.px + s2, c.py + s2};
-    if constexpr (NS > 0) {
-        a64_xy_run<E, R, ZS, NS>(acc, c, l, lds, std::make_integer_sequence<int, 4 * R * NS>{});
-    } else {
-#pragma unroll
-        for (int p = 1; p <= R; ++p) {
-            const int n0 = (l.px + p < c.dx) ? l.tid + p : c.npen;
-            axpy_pencil<double, E, ZS>(acc, c.cx[p], lds + n0 * ZS);
-            const int n1 = (l.px - p >= 0) ? l.tid - p : c.npen;
-            axpy_pencil<double, E, ZS>(acc, c.cx[p], lds + n1 * ZS);
-            const int n2 = (l.py + p < c.dy) ? l.tid + p * c.dx : c.npen;
-            axpy_pencil<double, E, ZS>(acc, c.cy[p], lds + n2 * ZS);
-            const int n3 = (l.py - p >= 0) ? l.tid - p * c.dx : c.npen;
-            axpy_pencil<double, E, ZS>(acc, c.cy[p], lds + n3 * ZS);
-        }
-    }
+    static_assert(NS > 0, "x/y units of the box");
+    a64_xy_run<E, R, ZS, NS>(acc, c, l, lds, std::make_integer_sequence<int, 4 * R * NS>{});
 }
 
 // the wave's largest column-entry count (the final pass runs every lane to it)
@@ -268,16 +300,17 @@ __device__ __forceinline__ double a64_wave_sum(double x) {
     return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
 }
 
-// in-box run of column (cx, cy) of atom slot sl: first row, LDS offset, length
-template <int ZS>
+// in-box run of column (cx, cy) of atom slot sl: first row, box pencil and
+// first plane, length
 __device__ __forceinline__ int a64_run(const RegionArgs<double> &a, const Slot &sl, int cx,
-                                       int cy, int dx, int dz, int &row, int &off) {
+                                       int cy, int dx, int dz, int &row, int &pen, int &zfirst) {
     const int64_t ci = 2 * ((int64_t)sl.col + (int64_t)cy * sl.bx + cx);
     const int r0 = a.colidx[ci], zc = a.colidx[ci + 1];
     const int z0 = sl.oz + (zc & 0xffff);
     const int zlo = max(z0, 0), zhi = min(z0 + (zc >> 16), dz);
     row = r0 + (zlo - z0);
-    off = ((sl.oy + cy) * dx + (sl.ox + cx)) * ZS + zlo;
+    pen = (sl.oy + cy) * dx + (sl.ox + cx);
+    zfirst = zlo;
     return max(zhi - zlo, 0);
 }
 
@@ -307,8 +340,8 @@ __device__ int a64_build_list(const RegionArgs<double> &a, const Slot *slots, in
         int cnt = 0;
         for (int q0 = 0; q0 < ncols; q0 += 64) {
             const int q = q0 + lane;
-            int n = 0, row, off;
-            if (q < ncols) n = a64_run<ZS>(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, off);
+            int n = 0, row, pen, zf;
+            if (q < ncols) n = a64_run(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, pen, zf);
             cnt += wave_sum(n);
         }
         if (lane == 0) acnt[j] = cnt;
@@ -334,8 +367,8 @@ __device__ int a64_build_list(const RegionArgs<double> &a, const Slot *slots, in
         int pos = 0;
         for (int q0 = 0; q0 < ncols; q0 += 64) {
             const int q = q0 + lane;
-            int n = 0, row = 0, off = 0;
-            if (q < ncols) n = a64_run<ZS>(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, off);
+            int n = 0, row = 0, pen = 0, zf = 0;
+            if (q < ncols) n = a64_run(a, sl, cx0 + q % wx, cy0 + q / wx, dx, dz, row, pen, zf);
             int inc = n;   // inclusive scan over the lanes
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -343,7 +376,7 @@ __device__ int a64_build_list(const RegionArgs<double> &a, const Slot *slots, in
                 if (lane >= o) inc += t;
             }
             for (int i = 0; i < n; ++i)
-                out[pos + inc - n + i] = make_int2(row + i, (off + i) | (j << 16));
+                out[pos + inc - n + i] = make_int2(row + i, a64_off<E>(pen, zf + i) | (j << 16));
             pos += __shfl(inc, 63, 64);
         }
         for (int e = cnt + lane; e < nj * A64_CHUNK; e += 64)
@@ -559,13 +592,13 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
     constexpr int EE = E * E;
     constexpr int DB = A64_DB;
     constexpr int NDB = (E + DB - 1) / DB;
-    if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
+    if (c.active) a64_box_put<E>(lds, threadIdx.x, cur);
     __syncthreads();
     if (c.nat && pend != 0.0) {
         a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP,
                                nl.scale, pend);
         __syncthreads();
-        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
+        if (c.active) a64_box_get<E, 0, E>(cur, lds, threadIdx.x);
     }
     if (c.active) {
         // z neighbours from the registers of cur (its last use in the step):
@@ -608,7 +641,7 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
         __builtin_amdgcn_sched_barrier(0);
         int s3 = 0;
         asm volatile("" : "+v"(s3));
-        const double *mw = c.mine + s3;
+        const int own = (int)threadIdx.x + s3;
 #pragma unroll
         for (int b = 0; b < NDB; ++b) {
             if (b + 1 < NDB) load_d(b + 1);
@@ -619,7 +652,7 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
                     // the completed v_k to its slot row, from the own-pencil value the
                     // diagonal term reads anyway: issued here, after the batch's loads,
                     // the stores stay in flight while the next batch is waited for
-                    const double vz = mw[z];
+                    const double vz = lds[a64_off<E>(own, z)];
                     nw[z] = fma(d[b][i], vz, nw[z]);
                     a64_st(Sr, svo, (in_row + (uint32_t)(z * EE)) * 8u, vz);
                 }
@@ -630,7 +663,7 @@ __device__ __forceinline__ void a64_step_d(const RegionArgs<double> &a,
     __syncthreads();
 #pragma unroll
     for (int z = 0; z < E; ++z) cur[z] = nw[z];
-    if (c.active) load_pencil<double, E, ZS>(c.mine, nw);
+    if (c.active) a64_box_get<E, 0, E>(nw, lds, threadIdx.x);
     if (first) {
 #pragma unroll
         for (int z = 0; z < E; ++z) cur[z] *= 0.5;
@@ -663,13 +696,13 @@ __device__ __forceinline__ void a64_finish_d(const RegionArgs<double> &a,
                                              __amdgpu_buffer_rsrc_t Sr, uint32_t svo,
                                              uint32_t in_row, double pend) {
     constexpr int EE = E * E;
-    if (c.active) store_pencil<double, E, ZS>(c.mine, cur);
+    if (c.active) a64_box_put<E>(lds, threadIdx.x, cur);
     __syncthreads();
     if (c.nat && pend != 0.0) {
         a64_am_update<A64_NCB>(a, L, lds, nl.pacc + (int64_t)(nl.par ^ 1) * nl.maxat * NP,
                                nl.scale, pend);
         __syncthreads();
-        if (c.active) load_pencil<double, E, ZS>(c.mine, cur);
+        if (c.active) a64_box_get<E, 0, E>(cur, lds, threadIdx.x);
     }
     if (c.active) {
 #pragma unroll
@@ -721,7 +754,8 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
     ColEntry *colbuf = reinterpret_cast<ColEntry *>(slots + AT);
     int2 *alist = reinterpret_cast<int2 *>(colbuf + BLOCK * MAXC);
     int *acnt = reinterpret_cast<int *>(alist + a64_list_cap<E>());
-    static_assert((int64_t)(E * E + 1) * ZS < 65536, "box offsets fit 16 bits");
+    static_assert(region_lds_elems<T, E>() == a64_xb<E>() + E * E + 1, "the box layout");
+    static_assert(region_lds_elems<T, E>() < 65536, "box offsets fit 16 bits");
 
     for (;;) {
         if (tid == 0) {
@@ -740,7 +774,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         const int npen = c.dx * c.dy;
         c.active = tid < npen;
         const int px = c.active ? tid % c.dx : 0, py = c.active ? tid / c.dx : 0;
-        for (int i = tid; i < (npen + 1) * ZS; i += BLOCK) lds[i] = 0.0;
+        for (int i = tid; i < region_lds_elems<T, E>(); i += BLOCK) lds[i] = 0.0;
         if (a.n_atoms) gather_atoms<T, AT, BLOCK>(a, it, slots, &s_nat);
         int gx = it.lo[0] + px, gy = it.lo[1] + py;
         if (a.periodic) {
@@ -753,7 +787,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         const int n2 = a.periodic ? a.N[2] : (1 << 30);
         const bool is_ctr = c.active && px == it.ctr[0] && py == it.ctr[1];
         const int cz0 = it.ctr[2];
-        c.mine = lds + tid * ZS;
+        c.mine = nullptr;   // the box is addressed through a64_off (split planes)
         c.px = px;
         c.py = py;
         c.npen = npen;
@@ -788,7 +822,7 @@ cheb_adjoint64_kernel(const AdjointArgs<double> aa) {
         A64List L{alist, 0, 0};
         if (c.nat) {
             const int nch = a64_build_list<E, ZS, BLOCK>(a, slots, c.nat, c.dx, c.dy, c.dz,
-                                                        npen * ZS, alist, acnt);
+                                                        a64_off<E>(npen, 0), alist, acnt);
             const int w = tid >> 6;
             L.g0 = w * nch / (BLOCK / 64);
             L.g1 = (w + 1) * nch / (BLOCK / 64);
