@@ -202,12 +202,25 @@ __device__ __forceinline__ void a64_box_put(double *lds, int n, const double (&v
     lds[a64_xb<E>() + n] = v[E - 1];
 }
 
+// units of a pencil: NS runs of planes of an even length (the last one shorter:
+// 10, 10, 7 at E = 27), so that every unit starts on a 16-byte plane pair and
+// reads only pairs (and plane E-1 from its own block).  Thirds of 9 planes put
+// an 8-byte read at an odd plane into two units in three, and 8-byte reads at
+// the even pencil stride meet in pairs on the LDS banks.
+template <int E, int NS>
+struct A64Units {
+    static constexpr int H = ((E + NS - 1) / NS + 1) / 2 * 2;   // planes per unit
+    static constexpr int z0(int k) { return k * H; }
+    static constexpr int hz(int k) { return k + 1 < NS ? H : E - k * H; }
+    using Buf = double[H];   // one unit of a neighbour pencil
+};
+
 template <int E, int R, int ZS, int NS, int U>
-__device__ __forceinline__ void a64_xy_load(double (&q)[(E + NS - 1) / NS],
+__device__ __forceinline__ void a64_xy_load(typename A64Units<E, NS>::Buf &q,
                                             const StepCtx<double, E, R> &c, const A64Lane &l,
                                             const double *lds) {
-    constexpr int HZ = (E + NS - 1) / NS;
-    constexpr int j = U / NS, p = j / 4 + 1, dir = j % 4, z0 = (U % NS) * HZ;
+    constexpr int HZ = A64Units<E, NS>::hz(U % NS);
+    constexpr int j = U / NS, p = j / 4 + 1, dir = j % 4, z0 = A64Units<E, NS>::z0(U % NS);
     int n;
     if constexpr (dir == 0) n = (l.px + p < c.dx) ? l.tid + p : c.npen;
     else if constexpr (dir == 1) n = (l.px - p >= 0) ? l.tid - p : c.npen;
@@ -217,20 +230,21 @@ __device__ __forceinline__ void a64_xy_load(double (&q)[(E + NS - 1) / NS],
 }
 
 template <int E, int R, int ZS, int NS, int U>
-__device__ __forceinline__ void a64_xy_unit(double (&acc)[E], double (&qa)[(E + NS - 1) / NS],
-                                            double (&qb)[(E + NS - 1) / NS],
+__device__ __forceinline__ void a64_xy_unit(double (&acc)[E], typename A64Units<E, NS>::Buf &qa,
+                                            typename A64Units<E, NS>::Buf &qb,
                                             const StepCtx<double, E, R> &c, const A64Lane &l,
                                             const double *lds) {
-    constexpr int HZ = (E + NS - 1) / NS;
+    constexpr int HZ = A64Units<E, NS>::hz(U % NS);
+    constexpr int HM = A64Units<E, NS>::H;
     constexpr int NU = 4 * R * NS;
     if constexpr (U + 1 < NU) {
         if constexpr ((U + 1) & 1) a64_xy_load<E, R, ZS, NS, U + 1>(qb, c, l, lds);
         else a64_xy_load<E, R, ZS, NS, U + 1>(qa, c, l, lds);
     }
     __builtin_amdgcn_sched_barrier(0);
-    constexpr int j = U / NS, p = j / 4 + 1, z0 = (U % NS) * HZ;
+    constexpr int j = U / NS, p = j / 4 + 1, z0 = A64Units<E, NS>::z0(U % NS);
     const double w = (j % 4 < 2) ? c.cx[p] : c.cy[p];
-    const double(&q)[HZ] = (U & 1) ? qb : qa;
+    const double(&q)[HM] = (U & 1) ? qb : qa;
 #pragma unroll
     for (int i = 0; i < HZ; ++i)
         if (z0 + i < E) acc[z0 + i] = fma(w, q[i], acc[z0 + i]);
@@ -241,7 +255,7 @@ template <int E, int R, int ZS, int NS, int... U>
 __device__ __forceinline__ void a64_xy_run(double (&acc)[E], const StepCtx<double, E, R> &c,
                                            const A64Lane &l, const double *lds,
                                            std::integer_sequence<int, U...>) {
-    double qa[(E + NS - 1) / NS], qb[(E + NS - 1) / NS];
+    double qa[A64Units<E, NS>::H], qb[A64Units<E, NS>::H];
     a64_xy_load<E, R, ZS, NS, 0>(qa, c, l, lds);
     (a64_xy_unit<E, R, ZS, NS, U>(acc, qa, qb, c, l, lds), ...);
 }
