@@ -144,8 +144,8 @@ __device__ __forceinline__ void a64_store_proj(const ColNL<double> &nl, int nat,
 }
 
 // x/y neighbours: acc += sum over the 4R neighbouring pencils of their
-// weight times the pencil, read from the LDS box in units of 1/NS pencil
-// through a two-deep pipeline: the reads of the next unit are in flight while
+// weight times the pencil, read from the LDS box in NS units of a pencil
+// (A64Units: runs of an even number of planes) through a two-deep pipeline: the reads of the next unit are in flight while
 // the FMAs of the current one run (left to itself the compiler issues the
 // reads one at a time, each waiting for the previous).  Every unit is its own
 // compile-time instance, so both buffers stay in registers.  A neighbour
